@@ -1,0 +1,182 @@
+/*
+ * hsrq.h -- batched robust solves of shifted Hessenberg systems on MI355X.
+ *
+ * Computes, for an unreduced real upper Hessenberg matrix H and many distinct
+ * shifts lambda_l (real, or complex given by one member of a conjugate pair),
+ * the solutions of (H - lambda_l I) x_l = b_l of arXiv 2101.05063 ("Robust
+ * level-3 BLAS inverse iteration from the Hessenberg matrix"): Henry's RQ
+ * sweep (Sec. 2.2, Algorithm 1) rearranged into tiles so that the
+ * back-substitution updates drawn from tiles of H shared by all shifts become
+ * matrix-matrix products (Sec. 3.1, eq. update; Algorithms 6 and 10), with
+ * power-of-two segment scale factors that keep every intermediate below the
+ * overflow threshold (Sec. 4.1, eq. robust-update), complex Givens rotations
+ * for complex shifts (Sec. 4.3, eq. cgivens), and the normalisation and
+ * back-transform of Algorithm 11.  It returns unit 2-norm vectors together
+ * with the binary scale of the true solution and a convergence flag
+ * (Sec. 4.2).  With b_l a starting vector and lambda_l an eigenvalue estimate,
+ * this is one step of inverse iteration and the outputs are eigenvectors.
+ *
+ * Conventions
+ *   - All matrices are FP64, column-major with a leading dimension (LAPACK).
+ *   - "device" pointers are HIP device memory of the handle's device;
+ *     "host" pointers are ordinary host memory.
+ *   - Column layout of X (Sec. 4.3): one column per real shift, two adjacent
+ *     columns [re im] per complex shift, in the order of the shift list.
+ *   - Calls are asynchronous on the handle's stream (hsrq_set_stream); device
+ *     outputs are valid once that stream has been synchronised.  Host inputs
+ *     (shift lists, problem descriptors) are consumed before the call returns.
+ *   - Return value: HSRQ_OK, or a negative status.  A status of -k from the
+ *     single-problem call means that its k-th argument is invalid (LAPACK
+ *     convention).  Per-shift outcomes are reported in info[], never by the
+ *     return value.
+ *   - The library allocates no device memory inside a solve: the caller passes
+ *     a workspace whose size is returned by the matching *_workspace_size
+ *     call.  The handle owns a small pinned host staging buffer for the plan.
+ *
+ * Per-shift info codes
+ *   0  converged: ||x_true||_2 / ||b||_2 >= 1 / (10 n eps ||H||_inf), the
+ *      paper's convergence test (Sec. 4.2) without assuming b = ||H|| eps e
+ *   1  not converged (the vector is still returned)
+ *   2  exactly singular: R(1,1) = 0; the vector is the null vector Q^H e_1,
+ *      scale_exp = INT32_MAX, scale_mant = 0
+ *   3  non-finite entry in H (Hessenberg part) or in the shift
+ *   4  H is not unreduced (a zero subdiagonal entry), which the method
+ *      assumes (Sec. 1)
+ */
+#ifndef HSRQ_H
+#define HSRQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HSRQ_OK = 0,
+    HSRQ_ERR_HIP = -1001,        /* a HIP runtime call failed */
+    HSRQ_ERR_WORKSPACE = -1002,  /* workspace missing, too small or misaligned */
+    HSRQ_ERR_ALLOC = -1003,      /* host staging allocation failed */
+    HSRQ_ERR_ARG = -1004,        /* invalid argument in a batched/serving call */
+    HSRQ_ERR_BUSY = -1005        /* serving: the request does not fit the budget */
+};
+
+typedef struct hsrq_handle_s* hsrq_handle_t;
+
+/*
+ * Options.  Zero-initialised options select the defaults.
+ *   nb            tile size b_r of Sec. 3.2 (rows and columns of an H tile):
+ *                 0 = autotuned; otherwise 32 or 64.
+ *   cols_per_block shifts-per-block b_c as columns: 0 = default (64).
+ *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
+ *                 matrix cores, then an FP64 residual check per shift with a
+ *                 fall back to the all-FP64 solve for shifts that fail it.
+ *   residual      1 = also compute the FP64 normalised residual
+ *                 ||H y - lambda y||_2 / (||H||_F ||y||_2) into resid[].
+ */
+typedef struct {
+    int nb;
+    int cols_per_block;
+    int precision;
+    int residual;
+    int reserved[4];
+} hsrq_opts_t;
+
+/* One problem of a batched call.  H, X, scale_exp, scale_mant, info and
+   resid are device pointers; wr and wi are host arrays of length m. */
+typedef struct {
+    int n;
+    const double* H;
+    int ldh;
+    int m;
+    const double* wr;
+    const double* wi;
+    double* X;
+    int ldx;
+    int32_t* scale_exp;
+    double* scale_mant;
+    int32_t* info;
+    double* resid;
+} hsrq_problem_t;
+
+/* Create a handle on HIP device `device` (the device is made current for the
+   call).  Ownership of *out passes to the caller; release with hsrq_destroy. */
+int hsrq_create(hsrq_handle_t* out, int device);
+
+/* Release the handle, its pinned staging buffer and cached plans. */
+int hsrq_destroy(hsrq_handle_t h);
+
+/* Set the HIP stream (a hipStream_t, e.g. torch.cuda.current_stream()) that
+   subsequent calls enqueue on.  NULL selects the null stream. */
+int hsrq_set_stream(hsrq_handle_t h, void* stream);
+
+/*
+ * Workspace query for hsrq_dhsrq3: bytes of device workspace for a problem
+ * of order n with the m shifts whose imaginary parts are wi (host, length m;
+ * only wi != 0 matters).  Returns HSRQ_OK and writes *bytes.
+ */
+int hsrq_workspace_size(hsrq_handle_t h, int n, int m, const double* wi,
+                        const hsrq_opts_t* opts, size_t* bytes);
+
+/*
+ * Solve (H - lambda_l I) x_l = b_l, l = 1..m, robustly (DHSRQ3, Algorithm 13,
+ * generalised to complex shifts as in Algorithm 15), and normalise.
+ *
+ *   n            order of H (n >= 1)                                    arg 2
+ *   H, ldh       device, n x n upper Hessenberg, ldh >= n; only the
+ *                Hessenberg part is read; H is not modified             3, 4
+ *   m            number of shifts (m >= 0)                              5
+ *   wr, wi       host, shift l = wr[l] + i wi[l]; a complex shift stands
+ *                for its conjugate pair; wi < 0 is accepted (the
+ *                conjugate is solved and the result conjugated back)    6, 7
+ *   X, ldx       device, n x ncols (ncols = #real + 2 #complex), in: the
+ *                right-hand sides / starting vectors b_l, out: the unit
+ *                2-norm vectors y_l = x_l / ||x_l||_2 in the same columns 8, 9
+ *   scale_exp,   device, length m: ||x_l||_2 = scale_mant[l] * 2^scale_exp[l]
+ *   scale_mant   with scale_mant in [0.5, 1) (exact binary exponent of the
+ *                true, unscaled solution, which may exceed the double range) 10, 11
+ *   info         device, length m, per-shift codes above                12
+ *   resid        device, length m, or NULL (see opts.residual)           13
+ *   work, work_bytes  device workspace, 256-byte aligned                14, 15
+ *   opts         options or NULL                                         16
+ */
+int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh,
+                int m, const double* wr, const double* wi,
+                double* X, int ldx,
+                int32_t* scale_exp, double* scale_mant, int32_t* info,
+                double* resid, void* work, size_t work_bytes,
+                const hsrq_opts_t* opts);
+
+/* Workspace query for hsrq_dhsrq3_batched (problems: host array of count
+   descriptors; only n, m and wi are read). */
+int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
+                                const hsrq_opts_t* opts, size_t* bytes);
+
+/*
+ * Many independent problems of uneven order in one launch sequence: every
+ * tile-column step of every problem runs in the same kernel launch as the
+ * steps of the others, and the whole sequence is one graph launch.
+ * problems: host array of count descriptors (device data pointers inside).
+ * Returns HSRQ_ERR_ARG if any descriptor is invalid.
+ */
+int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
+                        void* work, size_t work_bytes, const hsrq_opts_t* opts);
+
+/*
+ * Debug/parity view of the workspace after a single-problem call: device
+ * pointers to the recorded rotations (c, s and the diagonal of R; row k,
+ * column c at [k * ld + c], internal column order) and the final working
+ * columns (cross-overs entering each diagonal tile).  col_of[l] (host out,
+ * length m) gives the internal column of shift l.  Valid until the workspace
+ * is reused.
+ */
+int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts,
+                    void* work, const double** C, const double** S, const double** PHI,
+                    const double** V, int* ld, int* nb, int32_t* col_of);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSRQ_H */

@@ -1,0 +1,248 @@
+"""Python binding of ``libhsrq.so`` (batched robust shifted Hessenberg solves).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the library.  PyTorch provides device memory and the stream.  The raw C-ABI
+functions are available under their C names (``hsrq_create``, ``hsrq_dhsrq3``,
+...); ``Solver`` wraps them for torch tensors.
+
+There is no CPU fallback: importing works without a GPU (so that the library
+can be inspected), but any solve raises if the library or a GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsrq.so")
+
+HSRQ_OK = 0
+INFO_OK, INFO_NOT_CONVERGED, INFO_SINGULAR, INFO_NONFINITE, INFO_REDUCED = 0, 1, 2, 3, 4
+
+EXPORTED = [
+    "hsrq_create", "hsrq_destroy", "hsrq_set_stream", "hsrq_workspace_size", "hsrq_dhsrq3",
+    "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
+]
+
+
+class HsrqOpts(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("cols_per_block", ctypes.c_int), ("precision", ctypes.c_int),
+                ("residual", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+
+
+class HsrqProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int), ("m", ctypes.c_int),
+                ("wr", ctypes.c_void_p), ("wi", ctypes.c_void_p), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int),
+                ("scale_exp", ctypes.c_void_p), ("scale_mant", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhsrq.so and declare the C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.hsrq_create.argtypes = [P(vp), i]
+    lib.hsrq_destroy.argtypes = [vp]
+    lib.hsrq_set_stream.argtypes = [vp, vp]
+    lib.hsrq_workspace_size.argtypes = [vp, i, i, vp, P(HsrqOpts), P(sz)]
+    lib.hsrq_dhsrq3.argtypes = [vp, i, vp, i, i, vp, vp, vp, i, vp, vp, vp, vp, vp, sz, P(HsrqOpts)]
+    lib.hsrq_workspace_size_batched.argtypes = [vp, i, P(HsrqProblem), P(HsrqOpts), P(sz)]
+    lib.hsrq_dhsrq3_batched.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts)]
+    lib.hsrq_debug_view.argtypes = [vp, i, i, vp, P(HsrqOpts), vp, P(vp), P(vp), P(vp), P(vp), P(i), P(i), vp]
+    for f in EXPORTED:
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def __getattr__(name):
+    if name in EXPORTED:
+        return getattr(load_library(), name)
+    raise AttributeError(name)
+
+
+def _check(st, what):
+    if st != HSRQ_OK:
+        raise RuntimeError(f"{what} failed with status {st}")
+
+
+def _opts(nb=0, precision=0, residual=False):
+    o = HsrqOpts()
+    o.nb = int(nb or 0)
+    o.precision = int(precision)
+    o.residual = 1 if residual else 0
+    return o
+
+
+def ncols_of(wi) -> int:
+    wi = np.asarray(wi)
+    return int(np.sum(np.where(wi != 0.0, 2, 1)))
+
+
+def colmajor(t):
+    """A column-major view/copy of a 2-D torch tensor: returns (tensor, ld)."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    r, c = t.shape
+    if (t.stride(0) == 1 or r == 1) and (t.stride(1) >= max(1, r) or c == 1):
+        return t, max(1, r) if c == 1 else t.stride(1)
+    tc = t.t().contiguous().t()
+    return tc, max(1, r)
+
+
+class Solver:
+    """Handle + workspace management on one device, for torch tensors."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP library has no CPU fallback")
+        self.torch = torch
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.hsrq_create(ctypes.byref(h), device), "hsrq_create")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            self.lib.hsrq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        _check(self.lib.hsrq_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)), "hsrq_set_stream")
+
+    def workspace(self, nbytes):
+        torch = self.torch
+        if self._ws is None or self._ws.numel() < nbytes + 256:
+            self._ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        return aligned, self._ws.numel() - (aligned - base)
+
+    def workspace_size(self, n, wi, nb=0, precision=0):
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        o = _opts(nb, precision)
+        out = ctypes.c_size_t()
+        _check(self.lib.hsrq_workspace_size(self.h, n, wi.shape[0], wi.ctypes.data_as(ctypes.c_void_p),
+                                            ctypes.byref(o), ctypes.byref(out)), "hsrq_workspace_size")
+        return out.value
+
+    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, stream=None):
+        """Solve in place: X (device, n x ncols) holds the starting vectors and
+        receives the unit vectors.  Returns (scale_exp, scale_mant, info,
+        resid) device tensors of length m."""
+        torch = self.torch
+        n = H.shape[0]
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        m = wr.shape[0]
+        Hc, ldh = colmajor(H)
+        if X.shape[0] > 1 and X.stride(0) != 1:
+            raise ValueError("X must be column-major (X.stride(0) == 1), e.g. B.t().contiguous().t()")
+        ldx = X.stride(1) if X.shape[1] > 1 else n
+        ldx = max(ldx, n)
+        dev = H.device
+        E = torch.empty(m, dtype=torch.int32, device=dev)
+        mu = torch.empty(m, dtype=torch.float64, device=dev)
+        info = torch.empty(m, dtype=torch.int32, device=dev)
+        res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
+        o = _opts(nb, precision, residual)
+        need = self.workspace_size(n, wi, nb, precision)
+        wp, wb = self.workspace(need)
+        self._stream(stream)
+        st = self.lib.hsrq_dhsrq3(self.h, n, Hc.data_ptr(), ldh, m, wr.ctypes.data_as(ctypes.c_void_p),
+                                  wi.ctypes.data_as(ctypes.c_void_p), X.data_ptr(), ldx, E.data_ptr(),
+                                  mu.data_ptr(), info.data_ptr(), res.data_ptr() if res is not None else None,
+                                  ctypes.c_void_p(wp), wb, ctypes.byref(o))
+        _check(st, "hsrq_dhsrq3")
+        self._keep = (Hc,)  # keep a temporary column-major copy alive until the stream runs
+        return E, mu, info, res
+
+    def solve(self, H, wr, wi, B, **kw):
+        """Out-of-place: returns (Y, E, mu, info, resid) with Y column-major."""
+        Y = B.t().contiguous().t().clone()
+        E, mu, info, res = self.dhsrq3(H, wr, wi, Y, **kw)
+        return Y, E, mu, info, res
+
+    def batched(self, problems, nb=0, precision=0, residual=False, stream=None):
+        """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
+        solved in place).  Returns a list of (E, mu, info, resid)."""
+        torch = self.torch
+        count = len(problems)
+        arr = (HsrqProblem * max(count, 1))()
+        keep, outs = [], []
+        for p, pr in enumerate(problems):
+            Hc, ldh = colmajor(pr["H"])
+            wr = np.ascontiguousarray(pr["wr"], dtype=np.float64)
+            wi = np.ascontiguousarray(pr["wi"], dtype=np.float64)
+            X = pr["X"]
+            m = wr.shape[0]
+            dev = Hc.device
+            E = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+            mu = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+            info = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+            res = torch.empty(max(m, 1), dtype=torch.float64, device=dev) if residual else None
+            keep += [Hc, wr, wi]
+            outs.append((E[:m], mu[:m], info[:m], res[:m] if res is not None else None))
+            a = arr[p]
+            a.n, a.H, a.ldh, a.m = Hc.shape[0], Hc.data_ptr(), ldh, m
+            a.wr, a.wi = wr.ctypes.data, wi.ctypes.data
+            a.X, a.ldx = X.data_ptr(), (X.stride(1) if X.shape[1] > 1 else Hc.shape[0])
+            a.scale_exp, a.scale_mant, a.info = E.data_ptr(), mu.data_ptr(), info.data_ptr()
+            a.resid = res.data_ptr() if res is not None else None
+        o = _opts(nb, precision, residual)
+        need = ctypes.c_size_t()
+        _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
+               "hsrq_workspace_size_batched")
+        wp, wb = self.workspace(need.value)
+        self._stream(stream)
+        _check(self.lib.hsrq_dhsrq3_batched(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o)),
+               "hsrq_dhsrq3_batched")
+        self._keep = keep
+        return outs
+
+    def debug_view(self, n, wi, nb=0):
+        """After a single-problem call: device pointers of the recorded
+        rotations C, S, the diagonal PHI of R and the working columns V
+        (row-major n x ld, internal column order) as torch tensors, plus the
+        internal column of every shift."""
+        torch = self.torch
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        m = wi.shape[0]
+        o = _opts(nb)
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        ld, nbo = ctypes.c_int(), ctypes.c_int()
+        col_of = np.zeros(max(m, 1), dtype=np.int32)
+        wp = (self._ws.data_ptr() + 255) & ~255
+        _check(self.lib.hsrq_debug_view(self.h, n, m, wi.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o),
+                                        ctypes.c_void_p(wp), *[ctypes.byref(p) for p in ptrs],
+                                        ctypes.byref(ld), ctypes.byref(nbo),
+                                        col_of.ctypes.data_as(ctypes.c_void_p)), "hsrq_debug_view")
+        base = self._ws.data_ptr()
+        out = []
+        for p in ptrs:
+            off = p.value - base
+            assert off % 8 == 0
+            out.append(self._ws[off:off + 8 * n * ld.value].view(torch.float64).view(n, ld.value))
+        return dict(C=out[0], S=out[1], PHI=out[2], V=out[3], ld=ld.value, nb=nbo.value, col_of=col_of[:m])

@@ -1,0 +1,62 @@
+// hsrq_common.h -- shared definitions of the HIP library (device and host).
+//
+// Internal data layout (one problem of order n with ncols internal columns):
+//   * columns are reordered so that every complex shift occupies an aligned
+//     pair [re im] (complex shifts first, then real ones); a shift with a
+//     negative imaginary part is replaced by its conjugate (Sec. 4.3: one
+//     member per conjugate pair) and the result conjugated back;
+//   * vector arrays (working columns V, right-hand sides / solutions X,
+//     rotations C, S and diagonal PHI) are row-major n x ld, so that the 64
+//     lanes of a wave that own 64 consecutive columns touch one contiguous
+//     512-byte row segment;
+//   * tiles are aligned to the bottom-right corner of H: tile t (0-based)
+//     covers rows/columns [tstart(t), tend(t)), tend(t) = n - (N-1-t) nb, so
+//     only the top-left tile can be ragged (Sec. 3.2 assumes n = N b_r).
+#pragma once
+#include <stdint.h>
+
+namespace hsrq {
+
+constexpr int kTExp = 1000;        // stored magnitudes stay below 2^kTExp
+constexpr int kNegExp = -100000;   // exponent of zero
+constexpr int kSingExp = 1 << 29;  // segment exponent of an exactly singular R(1,1)
+constexpr int kCB = 64;            // columns per block (shifts-per-block b_c, in columns)
+
+enum ColType : int32_t { CT_REAL = 0, CT_CRE = 1, CT_CIM = 2 };
+enum TaskType : int32_t { TK_CHAIN = 0, TK_CRIT = 1, TK_FAR = 2 };
+enum FlagBits : int32_t { FL_NONFINITE = 1, FL_REDUCED = 2 };
+
+struct ProbDesc {
+  const double* H;
+  long long ldh;
+  int n, N, nb, ncols, ld, nblk, m, precision;
+  // workspace (device)
+  double *V, *X, *C, *S, *PHI, *Z0, *Z1;
+  double *BMAX, *VMAX, *TN, *BNORM, *HNP, *HFP, *RNUM;
+  int32_t *AX, *FLAGP;
+  // column metadata (device)
+  const double *lam_re, *lam_im;
+  const int32_t *coltype, *colshift, *colsrc, *colconj;
+  // caller outputs (device)
+  double* Xu;
+  long long ldx;
+  int32_t* Eu;
+  double* Mu;
+  int32_t* Iu;
+  double* Ru;
+};
+
+struct Task {
+  int32_t prob, type, i, L;
+};
+
+__host__ __device__ inline int tile_end(int n, int N, int nb, int t) { return n - (N - 1 - t) * nb; }
+__host__ __device__ inline int tile_start(int n, int N, int nb, int t) {
+  int e = tile_end(n, N, nb, t);
+  return e - nb > 0 ? e - nb : 0;
+}
+__host__ __device__ inline int tile_of_row(int n, int N, int nb, int r) {
+  return N - 1 - (n - 1 - r) / nb;
+}
+
+}  // namespace hsrq

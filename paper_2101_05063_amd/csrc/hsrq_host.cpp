@@ -1,0 +1,452 @@
+// hsrq_host.cpp -- C-ABI entry points, planning and launch sequence.
+//
+// A call plans on the host (column layout, tiling, per-step task lists,
+// workspace carving), copies the plan into the head of the caller's device
+// workspace with one asynchronous copy from a pinned staging buffer, and
+// enqueues the kernels on the handle's stream.  Nothing is allocated on the
+// device inside a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hsrq.h"
+#include "hsrq_common.h"
+
+namespace hsrq {
+void launch_prep(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
+void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
+void launch_bnorm(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
+void launch_step(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
+void launch_final(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
+void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
+void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
+void launch_fill(double* p, long long cnt, double v, hipStream_t st);
+}  // namespace hsrq
+
+using namespace hsrq;
+
+struct hsrq_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  hipEvent_t staging_ev = nullptr;
+  bool staging_pending = false;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  int ncols = 0;
+  std::vector<int32_t> coltype, colshift, colsrc, colconj;
+  std::vector<double> lr, li;
+};
+
+// Complex shifts first as aligned [re im] pairs, then real shifts, each group
+// in the caller's order (the real/complex split of Algorithm 15).
+Layout make_layout(int m, const double* wr, const double* wi) {
+  Layout L;
+  std::vector<int> ccol(m);
+  int c = 0;
+  for (int l = 0; l < m; ++l) {
+    ccol[l] = c;
+    c += (wi && wi[l] != 0.0) ? 2 : 1;
+  }
+  auto push = [&](int type, int shift, int src, int conj, double r, double i) {
+    L.coltype.push_back(type);
+    L.colshift.push_back(shift);
+    L.colsrc.push_back(src);
+    L.colconj.push_back(conj);
+    L.lr.push_back(r);
+    L.li.push_back(i);
+  };
+  for (int l = 0; l < m; ++l) {
+    if (!(wi && wi[l] != 0.0)) continue;
+    const bool bad = !std::isfinite(wr[l]) || !std::isfinite(wi[l]);
+    const int conj = (wi[l] < 0.0 ? 1 : 0) | (bad ? 2 : 0);
+    const double r = bad ? 0.0 : wr[l], i = bad ? 1.0 : std::fabs(wi[l]);
+    push(CT_CRE, l, ccol[l], conj, r, i);
+    push(CT_CIM, l, ccol[l] + 1, conj, r, i);
+  }
+  for (int l = 0; l < m; ++l) {
+    if (wi && wi[l] != 0.0) continue;
+    const bool bad = !std::isfinite(wr[l]) || (wi && !std::isfinite(wi[l]));
+    push(CT_REAL, l, ccol[l], bad ? 2 : 0, bad ? 0.0 : wr[l], 0.0);
+  }
+  L.ncols = (int)L.coltype.size();
+  return L;
+}
+
+int choose_nb(int n, const hsrq_opts_t* o) {
+  if (o && (o->nb == 32 || o->nb == 64)) return o->nb;
+  return n >= 512 ? 64 : 32;
+}
+
+struct ProbPlan {
+  int n, N, nb, ncols, ld, nblk;
+  Layout lay;
+  // byte offsets inside the workspace
+  size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
+  size_t o_V, o_X, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_TN, o_BNORM, o_HNP, o_HFP, o_RNUM, o_AX, o_FLAGP;
+};
+
+struct Plan {
+  int nb = 64;
+  std::vector<ProbPlan> pp;
+  std::vector<Task> tasks;
+  std::vector<int> toff, tcnt;
+  std::vector<int2> blk_prep, blk_cols;
+  std::vector<int4> blk_init, blk_out;
+  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout;
+  size_t head_bytes, total_bytes;
+  size_t o_rnum_all = 0, rnum_count = 0;
+};
+
+// Carve the workspace and build every host-side table.
+void build_plan(Plan& P, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
+  int nmax = 0;
+  for (int p = 0; p < count; ++p) nmax = std::max(nmax, probs[p].n);
+  P.nb = choose_nb(nmax, o);
+  const int nb = P.nb;
+  P.pp.resize(count);
+  int Tmax = 0;
+  for (int p = 0; p < count; ++p) {
+    ProbPlan& q = P.pp[p];
+    q.n = probs[p].n;
+    q.nb = nb;
+    q.N = (q.n + nb - 1) / nb;
+    q.lay = make_layout(probs[p].m, probs[p].wr, probs[p].wi);
+    q.ncols = q.lay.ncols;
+    q.ld = std::max(8, (q.ncols + 7) & ~7);
+    q.nblk = (q.ncols + kCB - 1) / kCB;
+    if (q.ncols > 0) Tmax = std::max(Tmax, q.N);
+  }
+  // tasks: step t = 0 chains the last tile; step t >= 1 works on tile column
+  // jt = N - t (critical tasks first, then far tasks)
+  P.toff.assign(Tmax, 0);
+  P.tcnt.assign(Tmax, 0);
+  for (int t = 0; t < Tmax; ++t) {
+    P.toff[t] = (int)P.tasks.size();
+    for (int p = 0; p < count; ++p) {
+      const ProbPlan& q = P.pp[p];
+      if (q.ncols == 0 || q.N <= t) continue;
+      for (int L = 0; L < q.nblk; ++L) {
+        if (t == 0)
+          P.tasks.push_back(Task{p, TK_CHAIN, q.N - 1, L});
+        else
+          P.tasks.push_back(Task{p, TK_CRIT, q.N - t - 1, L});
+      }
+    }
+    if (t > 0) {
+      for (int p = 0; p < count; ++p) {
+        const ProbPlan& q = P.pp[p];
+        if (q.ncols == 0 || q.N <= t) continue;
+        const int jt = q.N - t;
+        for (int i = 0; i < jt - 1; ++i)
+          for (int L = 0; L < q.nblk; ++L) P.tasks.push_back(Task{p, TK_FAR, i, L});
+      }
+    }
+    P.tcnt[t] = (int)P.tasks.size() - P.toff[t];
+  }
+  for (int p = 0; p < count; ++p) {
+    const ProbPlan& q = P.pp[p];
+    if (q.ncols == 0) continue;
+    for (int t = 0; t < q.N; ++t) {
+      P.blk_prep.push_back(int2{p, t});
+      for (int L = 0; L < q.nblk; ++L) P.blk_init.push_back(int4{p, t, L, 0});
+    }
+    for (int L = 0; L < q.nblk; ++L) P.blk_cols.push_back(int2{p, L});
+    for (int r = 0; r < (q.n + 63) / 64; ++r)
+      for (int L = 0; L < q.nblk; ++L) P.blk_out.push_back(int4{p, r, L, 0});
+  }
+  // head: descriptors, tables, column metadata
+  size_t off = 0;
+  P.o_desc = off; off = align_up(off + sizeof(ProbDesc) * std::max(count, 1));
+  P.o_tasks = off; off = align_up(off + sizeof(Task) * std::max<size_t>(P.tasks.size(), 1));
+  P.o_bprep = off; off = align_up(off + sizeof(int2) * std::max<size_t>(P.blk_prep.size(), 1));
+  P.o_bcols = off; off = align_up(off + sizeof(int2) * std::max<size_t>(P.blk_cols.size(), 1));
+  P.o_binit = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_init.size(), 1));
+  P.o_bout = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_out.size(), 1));
+  for (auto& q : P.pp) {
+    q.o_meta_d = off; off = align_up(off + sizeof(double) * 2 * q.ld);
+    q.o_meta_i = off; off = align_up(off + sizeof(int32_t) * 4 * q.ld);
+  }
+  P.head_bytes = off;
+  // residual accumulators, contiguous for one fill
+  P.o_rnum_all = off;
+  for (auto& q : P.pp) {
+    q.o_RNUM = off;
+    off += sizeof(double) * q.ld;
+    P.rnum_count += q.ld;
+  }
+  off = align_up(off);
+  for (auto& q : P.pp) {
+    const size_t vec = sizeof(double) * (size_t)q.n * q.ld;
+    q.o_V = off; off = align_up(off + vec);
+    q.o_X = off; off = align_up(off + vec);
+    q.o_C = off; off = align_up(off + vec);
+    q.o_S = off; off = align_up(off + vec);
+    q.o_PHI = off; off = align_up(off + vec);
+    q.o_Z0 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
+    q.o_Z1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
+    q.o_BMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
+    q.o_VMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
+    q.o_AX = off; off = align_up(off + sizeof(int32_t) * (size_t)q.N * q.ld);
+    q.o_TN = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.N);
+    q.o_BNORM = off; off = align_up(off + sizeof(double) * q.ld);
+    q.o_HNP = off; off = align_up(off + sizeof(double) * q.N);
+    q.o_HFP = off; off = align_up(off + sizeof(double) * q.N);
+    q.o_FLAGP = off; off = align_up(off + sizeof(int32_t) * q.N);
+  }
+  P.total_bytes = off;
+}
+
+int ensure_staging(hsrq_handle_t h, size_t bytes) {
+  if (h->staging_pending) {
+    if (hipEventSynchronize(h->staging_ev) != hipSuccess) return HSRQ_ERR_HIP;
+    h->staging_pending = false;
+  }
+  if (h->staging_bytes >= bytes) return HSRQ_OK;
+  if (h->staging) hipHostFree(h->staging);
+  h->staging = nullptr;
+  h->staging_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 20);
+  if (hipHostMalloc(&h->staging, want, hipHostMallocDefault) != hipSuccess) {
+    h->staging = nullptr;
+    return HSRQ_ERR_ALLOC;
+  }
+  h->staging_bytes = want;
+  return HSRQ_OK;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, size_t work_bytes,
+        const hsrq_opts_t* o) {
+  Plan P;
+  build_plan(P, count, probs, o);
+  if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
+    return HSRQ_ERR_WORKSPACE;
+  int st = ensure_staging(h, P.head_bytes);
+  if (st) return st;
+  char* hb = static_cast<char*>(h->staging);
+  std::memset(hb, 0, P.head_bytes);
+  // descriptors
+  std::vector<ProbDesc> descs(count);
+  for (int p = 0; p < count; ++p) {
+    const ProbPlan& q = P.pp[p];
+    const hsrq_problem_t& pr = probs[p];
+    ProbDesc& d = descs[p];
+    std::memset(&d, 0, sizeof(d));
+    d.H = pr.H;
+    d.ldh = pr.ldh;
+    d.n = q.n; d.N = q.N; d.nb = q.nb; d.ncols = q.ncols; d.ld = q.ld; d.nblk = q.nblk; d.m = pr.m;
+    d.precision = o ? o->precision : 0;
+    d.V = at<double>(work, q.o_V);
+    d.X = at<double>(work, q.o_X);
+    d.C = at<double>(work, q.o_C);
+    d.S = at<double>(work, q.o_S);
+    d.PHI = at<double>(work, q.o_PHI);
+    d.Z0 = at<double>(work, q.o_Z0);
+    d.Z1 = at<double>(work, q.o_Z1);
+    d.BMAX = at<double>(work, q.o_BMAX);
+    d.VMAX = at<double>(work, q.o_VMAX);
+    d.TN = at<double>(work, q.o_TN);
+    d.BNORM = at<double>(work, q.o_BNORM);
+    d.HNP = at<double>(work, q.o_HNP);
+    d.HFP = at<double>(work, q.o_HFP);
+    d.RNUM = at<double>(work, q.o_RNUM);
+    d.AX = at<int32_t>(work, q.o_AX);
+    d.FLAGP = at<int32_t>(work, q.o_FLAGP);
+    d.lam_re = at<double>(work, q.o_meta_d);
+    d.lam_im = at<double>(work, q.o_meta_d) + q.ld;
+    d.coltype = at<int32_t>(work, q.o_meta_i);
+    d.colshift = at<int32_t>(work, q.o_meta_i) + q.ld;
+    d.colsrc = at<int32_t>(work, q.o_meta_i) + 2 * q.ld;
+    d.colconj = at<int32_t>(work, q.o_meta_i) + 3 * q.ld;
+    d.Xu = pr.X;
+    d.ldx = pr.ldx;
+    d.Eu = pr.scale_exp;
+    d.Mu = pr.scale_mant;
+    d.Iu = pr.info;
+    d.Ru = pr.resid;
+    // metadata into the staging image
+    double* md = reinterpret_cast<double*>(hb + q.o_meta_d);
+    int32_t* mi = reinterpret_cast<int32_t*>(hb + q.o_meta_i);
+    for (int c = 0; c < q.ncols; ++c) {
+      md[c] = q.lay.lr[c];
+      md[q.ld + c] = q.lay.li[c];
+      mi[c] = q.lay.coltype[c];
+      mi[q.ld + c] = q.lay.colshift[c];
+      mi[2 * q.ld + c] = q.lay.colsrc[c];
+      mi[3 * q.ld + c] = q.lay.colconj[c];
+    }
+  }
+  std::memcpy(hb + P.o_desc, descs.data(), sizeof(ProbDesc) * count);
+  if (!P.tasks.empty()) std::memcpy(hb + P.o_tasks, P.tasks.data(), sizeof(Task) * P.tasks.size());
+  if (!P.blk_prep.empty()) std::memcpy(hb + P.o_bprep, P.blk_prep.data(), sizeof(int2) * P.blk_prep.size());
+  if (!P.blk_cols.empty()) std::memcpy(hb + P.o_bcols, P.blk_cols.data(), sizeof(int2) * P.blk_cols.size());
+  if (!P.blk_init.empty()) std::memcpy(hb + P.o_binit, P.blk_init.data(), sizeof(int4) * P.blk_init.size());
+  if (!P.blk_out.empty()) std::memcpy(hb + P.o_bout, P.blk_out.data(), sizeof(int4) * P.blk_out.size());
+
+  hipStream_t s = h->stream;
+  if (hipMemcpyAsync(work, hb, P.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
+  if (hipEventRecord(h->staging_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
+  h->staging_pending = true;
+  if (P.blk_cols.empty()) return HSRQ_OK;
+
+  const ProbDesc* dd = at<ProbDesc>(work, P.o_desc);
+  const Task* dt = at<Task>(work, P.o_tasks);
+  launch_prep(dd, at<int2>(work, P.o_bprep), (int)P.blk_prep.size(), s);
+  launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s);
+  launch_bnorm(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), s);
+  for (size_t t = 0; t < P.toff.size(); ++t)
+    if (P.tcnt[t] > 0) launch_step(P.nb, dd, dt + P.toff[t], P.tcnt[t], (int)t, s);
+  launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), s);
+  bool want_res = o && o->residual;
+  if (want_res) {
+    for (int p = 0; p < count; ++p)
+      if (!probs[p].resid) want_res = false;
+  }
+  if (want_res) {
+    launch_fill(at<double>(work, P.o_rnum_all), (long long)P.rnum_count, 0.0, s);
+    launch_resid(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), at<int2>(work, P.o_bcols),
+                 (int)P.blk_cols.size(), s);
+  }
+  launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
+  if (hipGetLastError() != hipSuccess) return HSRQ_ERR_HIP;
+  return HSRQ_OK;
+}
+
+int check_problem(const hsrq_problem_t& p) {
+  if (p.n < 1) return -2;
+  if (!p.H) return -3;
+  if (p.ldh < p.n) return -4;
+  if (p.m < 0) return -5;
+  if (p.m > 0 && !p.wr) return -6;
+  if (p.m > 0 && !p.wi) return -7;
+  if (p.m > 0 && !p.X) return -8;
+  if (p.ldx < p.n) return -9;
+  if (p.m > 0 && !p.scale_exp) return -10;
+  if (p.m > 0 && !p.scale_mant) return -11;
+  if (p.m > 0 && !p.info) return -12;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsrq_create(hsrq_handle_t* out, int device) {
+  if (!out) return -1;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return HSRQ_ERR_HIP;
+  hsrq_handle_t h = new (std::nothrow) hsrq_handle_s();
+  if (!h) return HSRQ_ERR_ALLOC;
+  h->device = device;
+  if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) {
+    delete h;
+    return HSRQ_ERR_HIP;
+  }
+  *out = h;
+  return HSRQ_OK;
+}
+
+int hsrq_destroy(hsrq_handle_t h) {
+  if (!h) return HSRQ_OK;
+  if (h->staging_pending) hipEventSynchronize(h->staging_ev);
+  if (h->staging) hipHostFree(h->staging);
+  if (h->staging_ev) hipEventDestroy(h->staging_ev);
+  delete h;
+  return HSRQ_OK;
+}
+
+int hsrq_set_stream(hsrq_handle_t h, void* stream) {
+  if (!h) return -1;
+  h->stream = static_cast<hipStream_t>(stream);
+  return HSRQ_OK;
+}
+
+int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
+                                const hsrq_opts_t* opts, size_t* bytes) {
+  if (!h || count < 0 || (count > 0 && !problems) || !bytes) return HSRQ_ERR_ARG;
+  for (int p = 0; p < count; ++p)
+    if (problems[p].n < 1 || problems[p].m < 0 || (problems[p].m > 0 && !problems[p].wi)) return HSRQ_ERR_ARG;
+  Plan P;
+  build_plan(P, count, problems, opts);
+  *bytes = P.total_bytes;
+  return HSRQ_OK;
+}
+
+int hsrq_workspace_size(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts,
+                        size_t* bytes) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (m < 0) return -3;
+  if (m > 0 && !wi) return -4;
+  if (!bytes) return -6;
+  std::vector<double> wr(m > 0 ? m : 1, 0.0);
+  hsrq_problem_t p{};
+  p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;
+  Plan P;
+  build_plan(P, 1, &p, opts);
+  *bytes = P.total_bytes;
+  return HSRQ_OK;
+}
+
+int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh, int m, const double* wr,
+                const double* wi, double* X, int ldx, int32_t* scale_exp, double* scale_mant,
+                int32_t* info, double* resid, void* work, size_t work_bytes, const hsrq_opts_t* opts) {
+  if (!h) return -1;
+  hsrq_problem_t p{n, H, ldh, m, wr, wi, X, ldx, scale_exp, scale_mant, info, resid};
+  int st = check_problem(p);
+  if (st) return st;
+  if (!work) return -14;
+  if (m == 0) return HSRQ_OK;
+  return run(h, 1, &p, work, work_bytes, opts);
+}
+
+int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work,
+                        size_t work_bytes, const hsrq_opts_t* opts) {
+  if (!h || count < 0 || (count > 0 && !problems)) return HSRQ_ERR_ARG;
+  for (int p = 0; p < count; ++p)
+    if (check_problem(problems[p])) return HSRQ_ERR_ARG;
+  if (count == 0) return HSRQ_OK;
+  return run(h, count, problems, work, work_bytes, opts);
+}
+
+int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts, void* work,
+                    const double** C, const double** S, const double** PHI, const double** V, int* ld,
+                    int* nb, int32_t* col_of) {
+  if (!h || n < 1 || m < 0 || (m > 0 && !wi) || !work) return HSRQ_ERR_ARG;
+  std::vector<double> wr(m > 0 ? m : 1, 0.0);
+  hsrq_problem_t p{};
+  p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;
+  Plan P;
+  build_plan(P, 1, &p, opts);
+  const ProbPlan& q = P.pp[0];
+  if (C) *C = at<double>(work, q.o_C);
+  if (S) *S = at<double>(work, q.o_S);
+  if (PHI) *PHI = at<double>(work, q.o_PHI);
+  if (V) *V = at<double>(work, q.o_V);
+  if (ld) *ld = q.ld;
+  if (nb) *nb = q.nb;
+  if (col_of) {
+    for (int c = 0; c < q.ncols; ++c)
+      if (q.lay.coltype[c] != CT_CIM) col_of[q.lay.colshift[c]] = c;
+  }
+  return HSRQ_OK;
+}
+
+}  // extern "C"
