@@ -175,6 +175,30 @@ int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_
                     void* work, const double** C, const double** S, const double** PHI,
                     const double** V, int* ld, int* nb, int32_t* col_of);
 
+/*
+ * Profiling (for benchmarks; off by default).  While enabled, every kernel
+ * launch of subsequent calls is bracketed by a pair of HIP events recorded
+ * on the handle's stream.  hsrq_profile_read synchronises the recorded
+ * events, writes per kernel family k (HSRQ_K_*) the accumulated milliseconds
+ * ms[k] and the number of launches launches[k] (host arrays of nkinds
+ * entries), and clears the accumulators.  Events are created by the library
+ * (host-side handles; no device memory).  The far-tile kernels of a call run
+ * on a second stream owned by the handle, forked from and joined back into
+ * the handle's stream with events, so that they overlap the critical chain.
+ */
+enum {
+    HSRQ_K_PREP = 0,    /* validity flags, norms of H and of its tiles */
+    HSRQ_K_INIT = 1,    /* working columns and right-hand sides */
+    HSRQ_K_CRIT = 2,    /* superdiagonal tile + diagonal Givens/solve chain */
+    HSRQ_K_FAR = 3,     /* off-diagonal tile updates (MFMA) and rotations */
+    HSRQ_K_FINAL = 4,   /* consistency scaling, norm, back-transform */
+    HSRQ_K_OUTPUT = 5,  /* copy-out in the caller's column layout */
+    HSRQ_K_RESID = 6,   /* optional FP64 residual */
+    HSRQ_K_COUNT = 7
+};
+int hsrq_profile_enable(hsrq_handle_t h, int on);
+int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

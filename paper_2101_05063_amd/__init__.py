@@ -24,7 +24,9 @@ INFO_OK, INFO_NOT_CONVERGED, INFO_SINGULAR, INFO_NONFINITE, INFO_REDUCED = 0, 1,
 EXPORTED = [
     "hsrq_create", "hsrq_destroy", "hsrq_set_stream", "hsrq_workspace_size", "hsrq_dhsrq3",
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
+    "hsrq_profile_enable", "hsrq_profile_read",
 ]
+KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
 
 class HsrqOpts(ctypes.Structure):
@@ -61,6 +63,8 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_workspace_size_batched.argtypes = [vp, i, P(HsrqProblem), P(HsrqOpts), P(sz)]
     lib.hsrq_dhsrq3_batched.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts)]
     lib.hsrq_debug_view.argtypes = [vp, i, i, vp, P(HsrqOpts), vp, P(vp), P(vp), P(vp), P(vp), P(i), P(i), vp]
+    lib.hsrq_profile_enable.argtypes = [vp, i]
+    lib.hsrq_profile_read.argtypes = [vp, i, vp, vp]
     for f in EXPORTED:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -221,6 +225,18 @@ class Solver:
                "hsrq_dhsrq3_batched")
         self._keep = keep
         return outs
+
+    def profile(self, on=True):
+        _check(self.lib.hsrq_profile_enable(self.h, 1 if on else 0), "hsrq_profile_enable")
+
+    def profile_read(self):
+        """{kind: (ms, launches)} accumulated since the last read."""
+        k = len(KERNEL_KINDS)
+        ms = np.zeros(k)
+        ln = np.zeros(k, dtype=np.int64)
+        _check(self.lib.hsrq_profile_read(self.h, k, ms.ctypes.data_as(ctypes.c_void_p),
+                                          ln.ctypes.data_as(ctypes.c_void_p)), "hsrq_profile_read")
+        return {name: (float(ms[i]), int(ln[i])) for i, name in enumerate(KERNEL_KINDS)}
 
     def debug_view(self, n, wi, nb=0):
         """After a single-problem call: device pointers of the recorded

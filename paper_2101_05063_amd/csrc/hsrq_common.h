@@ -31,9 +31,13 @@ struct ProbDesc {
   long long ldh;
   int n, N, nb, ncols, ld, nblk, m, precision;
   // workspace (device)
-  double *V, *X, *C, *S, *PHI, *Z0, *Z1;
-  double *BMAX, *VMAX, *TN, *BNORM, *HNP, *HFP, *RNUM;
-  int32_t *AX, *FLAGP;
+  double *V, *X, *Y, *C, *S, *PHI, *Z0, *Z1;
+  double *BMAX, *VMAX, *BSSQ, *BCMX, *TN, *FIN;
+  int32_t *AX, *AMAX;
+  // zero-initialised per call: row sums, ||H||_F^2, flags, residual sums
+  double *RSUM, *HF, *RNUM;
+  int32_t* FLAG;
+  double* HN;
   // column metadata (device)
   const double *lam_re, *lam_im;
   const int32_t *coltype, *colshift, *colsrc, *colconj;

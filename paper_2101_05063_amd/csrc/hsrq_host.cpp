@@ -12,17 +12,18 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "hsrq.h"
 #include "hsrq_common.h"
 
 namespace hsrq {
-void launch_prep(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
+void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_bnorm(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
-void launch_step(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
-void launch_final(const ProbDesc* d, const int2* blk, int nblk, hipStream_t st);
+void launch_crit(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
+void launch_far(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
+void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
 void launch_fill(double* p, long long cnt, double v, hipStream_t st);
@@ -37,6 +38,13 @@ struct hsrq_handle_s {
   size_t staging_bytes = 0;
   hipEvent_t staging_ev = nullptr;
   bool staging_pending = false;
+  // second stream for the far-tile kernels, and fork/join events
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> sync_ev;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 };
 
 namespace {
@@ -85,9 +93,12 @@ Layout make_layout(int m, const double* wr, const double* wi) {
   return L;
 }
 
+constexpr int kCrit = 16;   // columns of a critical task
+constexpr int kChunk = 128;  // rows per chunk of the final scan
+
 int choose_nb(int n, const hsrq_opts_t* o) {
-  if (o && (o->nb == 32 || o->nb == 64)) return o->nb;
-  return n >= 512 ? 64 : 32;
+  if (o && (o->nb == 64 || o->nb == 128)) return o->nb;
+  return n >= 2048 ? 128 : 64;
 }
 
 struct ProbPlan {
@@ -95,19 +106,20 @@ struct ProbPlan {
   Layout lay;
   // byte offsets inside the workspace
   size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
-  size_t o_V, o_X, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_TN, o_BNORM, o_HNP, o_HFP, o_RNUM, o_AX, o_FLAGP;
+  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
+  size_t o_zero, o_RSUM, o_HF, o_FLAG, o_RNUM, o_HN;
 };
 
 struct Plan {
   int nb = 64;
   std::vector<ProbPlan> pp;
   std::vector<Task> tasks;
-  std::vector<int> toff, tcnt;
-  std::vector<int2> blk_prep, blk_cols;
-  std::vector<int4> blk_init, blk_out;
-  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout;
+  std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
+  std::vector<int2> blk_cols;
+  std::vector<int4> blk_prep, blk_init, blk_out, blk_fin;
+  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin;
   size_t head_bytes, total_bytes;
-  size_t o_rnum_all = 0, rnum_count = 0;
+  size_t o_zero_all = 0, zero_count = 0;  // doubles
 };
 
 // Carve the workspace and build every host-side table.
@@ -131,20 +143,25 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, const hsrq_opts
   }
   // tasks: step t = 0 chains the last tile; step t >= 1 works on tile column
   // jt = N - t (critical tasks first, then far tasks)
-  P.toff.assign(Tmax, 0);
-  P.tcnt.assign(Tmax, 0);
+  P.coff.assign(Tmax, 0);
+  P.ccnt.assign(Tmax, 0);
+  P.foff.assign(Tmax, 0);
+  P.fcnt.assign(Tmax, 0);
   for (int t = 0; t < Tmax; ++t) {
-    P.toff[t] = (int)P.tasks.size();
+    P.coff[t] = (int)P.tasks.size();
     for (int p = 0; p < count; ++p) {
       const ProbPlan& q = P.pp[p];
       if (q.ncols == 0 || q.N <= t) continue;
-      for (int L = 0; L < q.nblk; ++L) {
+      const int ncrit = (q.ncols + kCrit - 1) / kCrit;
+      for (int L = 0; L < ncrit; ++L) {
         if (t == 0)
           P.tasks.push_back(Task{p, TK_CHAIN, q.N - 1, L});
         else
           P.tasks.push_back(Task{p, TK_CRIT, q.N - t - 1, L});
       }
     }
+    P.ccnt[t] = (int)P.tasks.size() - P.coff[t];
+    P.foff[t] = (int)P.tasks.size();
     if (t > 0) {
       for (int p = 0; p < count; ++p) {
         const ProbPlan& q = P.pp[p];
@@ -154,44 +171,54 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, const hsrq_opts
           for (int L = 0; L < q.nblk; ++L) P.tasks.push_back(Task{p, TK_FAR, i, L});
       }
     }
-    P.tcnt[t] = (int)P.tasks.size() - P.toff[t];
+    P.fcnt[t] = (int)P.tasks.size() - P.foff[t];
   }
   for (int p = 0; p < count; ++p) {
     const ProbPlan& q = P.pp[p];
     if (q.ncols == 0) continue;
     for (int t = 0; t < q.N; ++t) {
-      P.blk_prep.push_back(int2{p, t});
+      for (int jt = t; jt < q.N; ++jt) P.blk_prep.push_back(int4{p, t, jt, 0});
       for (int L = 0; L < q.nblk; ++L) P.blk_init.push_back(int4{p, t, L, 0});
     }
     for (int L = 0; L < q.nblk; ++L) P.blk_cols.push_back(int2{p, L});
     for (int r = 0; r < (q.n + 63) / 64; ++r)
       for (int L = 0; L < q.nblk; ++L) P.blk_out.push_back(int4{p, r, L, 0});
+    const int nch = (q.n + kChunk - 1) / kChunk;
+    for (int g = 0; g < (nch + 3) / 4; ++g)
+      for (int L = 0; L < q.nblk; ++L) P.blk_fin.push_back(int4{p, g, L, 0});
   }
   // head: descriptors, tables, column metadata
   size_t off = 0;
   P.o_desc = off; off = align_up(off + sizeof(ProbDesc) * std::max(count, 1));
   P.o_tasks = off; off = align_up(off + sizeof(Task) * std::max<size_t>(P.tasks.size(), 1));
-  P.o_bprep = off; off = align_up(off + sizeof(int2) * std::max<size_t>(P.blk_prep.size(), 1));
+  P.o_bprep = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_prep.size(), 1));
   P.o_bcols = off; off = align_up(off + sizeof(int2) * std::max<size_t>(P.blk_cols.size(), 1));
   P.o_binit = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_init.size(), 1));
   P.o_bout = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_out.size(), 1));
+  P.o_bfin = off; off = align_up(off + sizeof(int4) * std::max<size_t>(P.blk_fin.size(), 1));
   for (auto& q : P.pp) {
     q.o_meta_d = off; off = align_up(off + sizeof(double) * 2 * q.ld);
     q.o_meta_i = off; off = align_up(off + sizeof(int32_t) * 4 * q.ld);
   }
   P.head_bytes = off;
-  // residual accumulators, contiguous for one fill
-  P.o_rnum_all = off;
+  // zero-initialised accumulators of every problem, contiguous for one fill:
+  // row sums (n), ||H||_F^2 (1), flags (1 slot), ||H||_inf (1), residual sums (ld)
+  P.o_zero_all = off;
   for (auto& q : P.pp) {
-    q.o_RNUM = off;
-    off += sizeof(double) * q.ld;
-    P.rnum_count += q.ld;
+    q.o_zero = off;
+    q.o_RSUM = off; off += sizeof(double) * q.n;
+    q.o_HF = off; off += sizeof(double);
+    q.o_FLAG = off; off += sizeof(double);
+    q.o_HN = off; off += sizeof(double);
+    q.o_RNUM = off; off += sizeof(double) * q.ld;
   }
+  P.zero_count = (off - P.o_zero_all) / sizeof(double);
   off = align_up(off);
   for (auto& q : P.pp) {
     const size_t vec = sizeof(double) * (size_t)q.n * q.ld;
     q.o_V = off; off = align_up(off + vec);
     q.o_X = off; off = align_up(off + vec);
+    q.o_Y = off; off = align_up(off + vec);
     q.o_C = off; off = align_up(off + vec);
     q.o_S = off; off = align_up(off + vec);
     q.o_PHI = off; off = align_up(off + vec);
@@ -199,12 +226,13 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, const hsrq_opts
     q.o_Z1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
     q.o_BMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_VMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
+    q.o_BSSQ = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
+    q.o_BCMX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_AX = off; off = align_up(off + sizeof(int32_t) * (size_t)q.N * q.ld);
+    q.o_AMAX = off; off = align_up(off + sizeof(int32_t) * q.ld);
     q.o_TN = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.N);
-    q.o_BNORM = off; off = align_up(off + sizeof(double) * q.ld);
-    q.o_HNP = off; off = align_up(off + sizeof(double) * q.N);
-    q.o_HFP = off; off = align_up(off + sizeof(double) * q.N);
-    q.o_FLAGP = off; off = align_up(off + sizeof(int32_t) * q.N);
+    const size_t nch = (q.n + kChunk - 1) / kChunk;
+    q.o_FIN = off; off = align_up(off + sizeof(double) * (nch * 8 + 1) * q.ld);
   }
   P.total_bytes = off;
 }
@@ -226,6 +254,35 @@ int ensure_staging(hsrq_handle_t h, size_t bytes) {
   h->staging_bytes = want;
   return HSRQ_OK;
 }
+
+// Bracket one launch with profiling events when enabled.
+struct ProfScope {
+  hsrq_handle_t h;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hsrq_handle_t h_, int k, hipStream_t s_ = nullptr) : h(h_), kind(k), st(s_ ? s_ : h_->stream) {
+    if (!h->prof) return;
+    a = get();
+    b = get();
+    if (a) hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!h->prof || !a || !b) return;
+    hipEventRecord(b, st);
+    h->ev_used.push_back({kind, {a, b}});
+  }
+  hipEvent_t get() {
+    if (!h->ev_pool.empty()) {
+      hipEvent_t e = h->ev_pool.back();
+      h->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
 
 template <class T>
 T* at(void* base, size_t off) {
@@ -255,6 +312,7 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
     d.precision = o ? o->precision : 0;
     d.V = at<double>(work, q.o_V);
     d.X = at<double>(work, q.o_X);
+    d.Y = at<double>(work, q.o_Y);
     d.C = at<double>(work, q.o_C);
     d.S = at<double>(work, q.o_S);
     d.PHI = at<double>(work, q.o_PHI);
@@ -262,13 +320,17 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
     d.Z1 = at<double>(work, q.o_Z1);
     d.BMAX = at<double>(work, q.o_BMAX);
     d.VMAX = at<double>(work, q.o_VMAX);
+    d.BSSQ = at<double>(work, q.o_BSSQ);
+    d.BCMX = at<double>(work, q.o_BCMX);
     d.TN = at<double>(work, q.o_TN);
-    d.BNORM = at<double>(work, q.o_BNORM);
-    d.HNP = at<double>(work, q.o_HNP);
-    d.HFP = at<double>(work, q.o_HFP);
-    d.RNUM = at<double>(work, q.o_RNUM);
+    d.FIN = at<double>(work, q.o_FIN);
     d.AX = at<int32_t>(work, q.o_AX);
-    d.FLAGP = at<int32_t>(work, q.o_FLAGP);
+    d.AMAX = at<int32_t>(work, q.o_AMAX);
+    d.RSUM = at<double>(work, q.o_RSUM);
+    d.HF = at<double>(work, q.o_HF);
+    d.FLAG = at<int32_t>(work, q.o_FLAG);
+    d.HN = at<double>(work, q.o_HN);
+    d.RNUM = at<double>(work, q.o_RNUM);
     d.lam_re = at<double>(work, q.o_meta_d);
     d.lam_im = at<double>(work, q.o_meta_d) + q.ld;
     d.coltype = at<int32_t>(work, q.o_meta_i);
@@ -295,7 +357,8 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
   }
   std::memcpy(hb + P.o_desc, descs.data(), sizeof(ProbDesc) * count);
   if (!P.tasks.empty()) std::memcpy(hb + P.o_tasks, P.tasks.data(), sizeof(Task) * P.tasks.size());
-  if (!P.blk_prep.empty()) std::memcpy(hb + P.o_bprep, P.blk_prep.data(), sizeof(int2) * P.blk_prep.size());
+  if (!P.blk_prep.empty()) std::memcpy(hb + P.o_bprep, P.blk_prep.data(), sizeof(int4) * P.blk_prep.size());
+  if (!P.blk_fin.empty()) std::memcpy(hb + P.o_bfin, P.blk_fin.data(), sizeof(int4) * P.blk_fin.size());
   if (!P.blk_cols.empty()) std::memcpy(hb + P.o_bcols, P.blk_cols.data(), sizeof(int2) * P.blk_cols.size());
   if (!P.blk_init.empty()) std::memcpy(hb + P.o_binit, P.blk_init.data(), sizeof(int4) * P.blk_init.size());
   if (!P.blk_out.empty()) std::memcpy(hb + P.o_bout, P.blk_out.data(), sizeof(int4) * P.blk_out.size());
@@ -308,23 +371,59 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
 
   const ProbDesc* dd = at<ProbDesc>(work, P.o_desc);
   const Task* dt = at<Task>(work, P.o_tasks);
-  launch_prep(dd, at<int2>(work, P.o_bprep), (int)P.blk_prep.size(), s);
-  launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s);
-  launch_bnorm(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), s);
-  for (size_t t = 0; t < P.toff.size(); ++t)
-    if (P.tcnt[t] > 0) launch_step(P.nb, dd, dt + P.toff[t], P.tcnt[t], (int)t, s);
-  launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), s);
+  {
+    ProfScope ps(h, HSRQ_K_PREP);
+    launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
+    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, s);
+  }
+  { ProfScope ps(h, HSRQ_K_INIT); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
+  // steps: critical tasks on the handle's stream, far tasks on the second
+  // stream; step t of either kind waits for both kinds of step t-1
+  const int T = (int)P.coff.size();
+  if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
+  while ((int)h->sync_ev.size() < 2 * T + 2) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return HSRQ_ERR_HIP;
+    h->sync_ev.push_back(e);
+  }
+  hipStream_t a = h->aux;
+  hipEvent_t* ev = h->sync_ev.data();
+  // ev[2t]: critical step t done; ev[2t+1]: far step t done; ev[2T]: fork
+  hipEventRecord(ev[2 * T], s);
+  hipStreamWaitEvent(a, ev[2 * T], 0);
+  for (int t = 0; t < T; ++t) {
+    if (t > 0) {
+      hipStreamWaitEvent(s, ev[2 * (t - 1) + 1], 0);
+      hipStreamWaitEvent(a, ev[2 * (t - 1)], 0);
+    }
+    if (P.ccnt[t] > 0) {
+      ProfScope ps(h, HSRQ_K_CRIT, s);
+      launch_crit(P.nb, dd, dt + P.coff[t], P.ccnt[t], t, s);
+    }
+    if (P.fcnt[t] > 0) {
+      ProfScope ps(h, HSRQ_K_FAR, a);
+      launch_far(P.nb, dd, dt + P.foff[t], P.fcnt[t], t, a);
+    }
+    hipEventRecord(ev[2 * t], s);
+    hipEventRecord(ev[2 * t + 1], a);
+  }
+  if (T > 0) hipStreamWaitEvent(s, ev[2 * (T - 1) + 1], 0);
+  {
+    ProfScope ps(h, HSRQ_K_FINAL);
+    launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), at<int4>(work, P.o_bfin),
+                 (int)P.blk_fin.size(), s);
+  }
   bool want_res = o && o->residual;
   if (want_res) {
     for (int p = 0; p < count; ++p)
       if (!probs[p].resid) want_res = false;
   }
   if (want_res) {
-    launch_fill(at<double>(work, P.o_rnum_all), (long long)P.rnum_count, 0.0, s);
+    ProfScope ps(h, HSRQ_K_RESID);
     launch_resid(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), at<int2>(work, P.o_bcols),
                  (int)P.blk_cols.size(), s);
   }
-  launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
+  { ProfScope ps(h, HSRQ_K_OUTPUT); launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s); }
   if (hipGetLastError() != hipSuccess) return HSRQ_ERR_HIP;
   return HSRQ_OK;
 }
@@ -363,9 +462,49 @@ int hsrq_create(hsrq_handle_t* out, int device) {
   return HSRQ_OK;
 }
 
+int hsrq_profile_enable(hsrq_handle_t h, int on) {
+  if (!h) return -1;
+  h->prof = on != 0;
+  return HSRQ_OK;
+}
+
+int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches) {
+  if (!h || nkinds < 0 || (nkinds > 0 && (!ms || !launches))) return -1;
+  for (int k = 0; k < nkinds; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int st = HSRQ_OK;
+  for (auto& u : h->ev_used) {
+    float t = 0.f;
+    if (hipEventSynchronize(u.second.second) != hipSuccess ||
+        hipEventElapsedTime(&t, u.second.first, u.second.second) != hipSuccess)
+      st = HSRQ_ERR_HIP;
+    if (u.first < nkinds) {
+      ms[u.first] += t;
+      launches[u.first] += 1;
+    }
+    h->ev_pool.push_back(u.second.first);
+    h->ev_pool.push_back(u.second.second);
+  }
+  h->ev_used.clear();
+  return st;
+}
+
 int hsrq_destroy(hsrq_handle_t h) {
   if (!h) return HSRQ_OK;
   if (h->staging_pending) hipEventSynchronize(h->staging_ev);
+  for (auto& u : h->ev_used) {
+    hipEventSynchronize(u.second.second);
+    h->ev_pool.push_back(u.second.first);
+    h->ev_pool.push_back(u.second.second);
+  }
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
+  if (h->aux) {
+    hipStreamSynchronize(h->aux);
+    hipStreamDestroy(h->aux);
+  }
   if (h->staging) hipHostFree(h->staging);
   if (h->staging_ev) hipEventDestroy(h->staging_ev);
   delete h;

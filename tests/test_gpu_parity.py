@@ -59,8 +59,8 @@ def random_shifts(rng, H, nreal, ncplx, neg=False):
 # ---------------------------------------------------------------------------
 # rotations, diagonal of R and working columns: bit for bit
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("nb", [32, 64])
-@pytest.mark.parametrize("n", [150, 64, 7])
+@pytest.mark.parametrize("nb", [64, 128])
+@pytest.mark.parametrize("n", [300, 150, 64, 7])
 def test_rotations_bitwise(solver, n, nb):
     rng = np.random.default_rng(n * 7 + nb)
     H = g.random_hessenberg(n, rng)
@@ -101,8 +101,8 @@ def test_rotations_bitwise(solver, n, nb):
 # ---------------------------------------------------------------------------
 # solutions: random shifts (far from the spectrum or not), several tilings
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n,nb", [(1, 32), (2, 32), (5, 32), (31, 32), (32, 32), (33, 32), (64, 64),
-                                  (65, 64), (130, 32), (200, 64), (333, 64)])
+@pytest.mark.parametrize("n,nb", [(1, 64), (2, 64), (5, 128), (63, 64), (64, 64), (65, 64), (127, 128),
+                                  (128, 128), (129, 128), (200, 64), (333, 128), (700, 64)])
 def test_random_parity(solver, n, nb):
     rng = np.random.default_rng(1000 + n)
     H = g.random_hessenberg(n, rng)
@@ -206,7 +206,7 @@ def test_batched_uneven(solver):
         B = rng.standard_normal((n, g.ncols(wi)))
         probs.append(dict(H=dev(H), wr=wr, wi=wi, X=dev(B)))
         host_probs.append((H, wr, wi, B))
-    outs = solver.batched(probs, nb=32)
+    outs = solver.batched(probs, nb=64)
     torch.cuda.synchronize()
     for pr, (H, wr, wi, B), (E, mu, info, _) in zip(probs, host_probs, outs):
         Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
