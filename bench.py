@@ -10,9 +10,14 @@ starting vectors all ones.  One step = one complete solve of the 1000 shifts
 (every kernel of the path), with H, shifts and starting vectors already
 resident in device memory.
 
-Prints one JSON line.  ``roofline`` is for the step kernel (the tile-column
-kernel that holds the rotations, the tile updates and the diagonal chains),
-timed live with HIP events recorded by the library around each launch.
+Prints one JSON line.  ``roofline`` is for the kernel family with the
+largest measured time per solve (the critical kernel: superdiagonal tile and
+diagonal chain, or the far-tile kernel: off-diagonal tile updates and
+rotations), timed live with HIP events that the library records on the
+stream of each launch; ``kernels`` gives both.  ``traffic`` (HBM bytes per
+launch) comes from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs committed
+under profiles/, calibrated against a plain device copy (``--copy-probe``),
+and is null when the kernel sources changed since they were taken.
 """
 from __future__ import annotations
 
@@ -70,16 +75,181 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per step-kernel launch from committed rocprofv3 counter runs,
-    valid only for the kernel sources they were taken on."""
-    p = os.path.join(ROOT, "profiles", "traffic_k_step_c3.json")
-    if not os.path.exists(p):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, valid
+    only for the kernel sources they were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    d = json.load(open(p))
+    d = json.load(open(TRAFFIC_FILE))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def _pmc_rows(path):
+    """(kernel name, counter value) rows of a rocprofv3 counter_collection.csv."""
+    import csv
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def ingest_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
+    """Writes profiles/traffic_c3.json from two counter runs of the benchmark
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) and the same two counters
+    read on the plain copy of --copy-probe, whose true traffic is copy_bytes
+    read and copy_bytes written per dispatch."""
+    import statistics
+
+    def per_kernel(rows):
+        acc = {}
+        for name, v in rows:
+            key = name.split("(")[0].replace("void ", "").strip()
+            acc.setdefault(key, []).append(v)
+        return acc
+
+    def copy_value(rows):
+        vals = [v for name, v in rows if "copy" in name.lower()]
+        return statistics.median(vals)
+
+    f_copy = copy_value(_pmc_rows(copy_fetch_csv)) * 1024.0
+    w_copy = copy_value(_pmc_rows(copy_write_csv)) * 1024.0
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    fk, wk = per_kernel(_pmc_rows(fetch_csv)), per_kernel(_pmc_rows(write_csv))
+    kernels = {}
+    for k in fk:
+        if k in wk:
+            fb = statistics.mean(fk[k]) * 1024.0 * f_scale
+            wb = statistics.mean(wk[k]) * 1024.0 * w_scale
+            kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                          "bytes_per_launch": fb + wb, "launches": len(fk[k])}
+    d = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+         "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps(d, indent=1, sort_keys=True))
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_probe():
+    """A plain device copy of known size for calibrating the HBM counters."""
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
+
+
+def cpu_baseline(c, seconds, cores):
+    """The plain C reference on a bounded sample of the same shifts: passes
+    over leading shifts of the list, sized so that the sample takes about
+    `seconds` of wall time on `cores` threads (the whole list is used, more
+    than once if one pass is shorter than that)."""
+    from oracle import oracle as O
+    H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    O.build()
+    k = max(1, cores)
+    t0 = time.perf_counter()
+    O.batch(H, wr[:k], wi[:k], B[:, :k], nthreads=cores)
+    per_round = max(time.perf_counter() - t0, 1e-3)
+    want = max(1, int(seconds / per_round)) * k
+    done, dt = 0, 0.0
+    t0 = time.perf_counter()
+    while done < want:
+        s = min(len(wr), want - done)
+        O.batch(H, wr[:s], wi[:s], B[:, :s], nthreads=cores)
+        done += s
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="eigenvectors/s", cores=cores, kind="oracle",
+                sample=f"{done} solves over the leading shifts of the {len(wr)}-shift list (n={H.shape[0]}), "
+                       f"{dt:.1f} s wall on {cores} threads")
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, valid
+    only for the kernel sources they were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    d = json.load(open(TRAFFIC_FILE))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def _pmc_rows(path):
+    """(kernel name, counter value) rows of a rocprofv3 counter_collection.csv."""
+    import csv
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def ingest_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
+    """Writes profiles/traffic_c3.json from two counter runs of the benchmark
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) and the same two counters
+    read on the plain copy of --copy-probe, whose true traffic is copy_bytes
+    read and copy_bytes written per dispatch."""
+    import statistics
+
+    def per_kernel(rows):
+        acc = {}
+        for name, v in rows:
+            key = name.split("(")[0].replace("void ", "").strip()
+            acc.setdefault(key, []).append(v)
+        return acc
+
+    def copy_value(rows):
+        vals = [v for name, v in rows if "copy" in name.lower()]
+        return statistics.median(vals)
+
+    f_copy = copy_value(_pmc_rows(copy_fetch_csv)) * 1024.0
+    w_copy = copy_value(_pmc_rows(copy_write_csv)) * 1024.0
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    fk, wk = per_kernel(_pmc_rows(fetch_csv)), per_kernel(_pmc_rows(write_csv))
+    kernels = {}
+    for k in fk:
+        if k in wk:
+            fb = statistics.mean(fk[k]) * 1024.0 * f_scale
+            wb = statistics.mean(wk[k]) * 1024.0 * w_scale
+            kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                          "bytes_per_launch": fb + wb, "launches": len(fk[k])}
+    d = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+         "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps(d, indent=1, sort_keys=True))
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_probe():
+    """A plain device copy of known size for calibrating the HBM counters."""
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
 
 
 def cpu_baseline(c, seconds, cores):
@@ -109,13 +279,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_c3.json from rocprofv3 counter_collection.csv files")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc, COPY_BYTES)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the path shards over shifts with no communication, "
               "and this build runs and reports a single MI355X only (use --gpus 1).", flush=True)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import numpy as np
     import torch
@@ -157,18 +337,26 @@ def main():
     # the tile size the library chose (same rule as the host planner)
     nbv = nb if nb in (64, 128) else (128 if n >= 2048 else 64)
     fl = table1_flops(n, nbv, wi)
-    far_ms, far_launch = prof["far"]
-    crit_ms, crit_launch = prof["crit"]
-    far_per_solve = far_ms / args.steps
-    achieved = fl["far"] / (far_per_solve * 1e-3) / 1e12  # TFLOP/s over every far launch of a solve
-    traffic = load_traffic()
-    roof = {"kernel": f"hsrq::k_far<{nbv}>", "bound": "alu", "achieved": round(achieved, 3),
-            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-            "traffic": traffic,
-            "avg_launch_ms": round(far_ms / far_launch, 5) if far_launch else None,
-            "launches_per_step": far_launch / args.steps,
-            "flops_per_launch": fl["far"] / (far_launch / args.steps) if far_launch else None}
+    kern = {}
+    for kind, fam in (("crit", "k_crit"), ("far", "k_far")):
+        ms_k, launches = prof[kind]
+        per_solve = ms_k / args.steps
+        name = f"hsrq::{fam}<{nbv}>"
+        ach = fl[kind] / (per_solve * 1e-3) / 1e12 if per_solve > 0 else 0.0
+        kern[kind] = {"kernel": name, "ms_per_step": round(per_solve, 4),
+                      "launches_per_step": launches / args.steps,
+                      "avg_launch_ms": round(ms_k / launches, 5) if launches else None,
+                      "flops_per_launch": fl[kind] / (launches / args.steps) if launches else None,
+                      "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK_FP64_TFLOPS, 4)}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    dk = kern[dom]
+    roof = {"kernel": dk["kernel"], "bound": "alu", "achieved": dk["achieved_tflops"],
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": dk["frac_fp64_peak"],
+            "traffic": load_traffic(dk["kernel"]),
+            "avg_launch_ms": dk["avg_launch_ms"], "launches_per_step": dk["launches_per_step"],
+            "flops_per_launch": dk["flops_per_launch"]}
     value = m / (ms * 1e-3)
+    tile_ms = (prof["far"][0] + prof["crit"][0]) / args.steps
     line = {
         "metric": "eigenvectors/s (n=8000, m=1000; + % FP64 MFMA peak of the level-3 update)",
         "value": round(value, 2), "unit": "eigenvectors/s", "n_gpus": 1, "steps": args.steps,
@@ -178,13 +366,11 @@ def main():
                                "all-ones starts (D_ii = 10^(300 i/n))",
                    "n": n, "m": m, "nb": nbv, "precision": args.precision},
         "roofline": roof,
+        "kernels": kern,
         "level3_update": {"flops": fl["update"],
                           "frac_fp64_mfma_peak_over_tile_kernel_time":
-                              round(fl["update"] / ((far_ms + crit_ms) / args.steps * 1e-3) / 1e12
-                                    / PEAK_FP64_TFLOPS, 4)},
-        "crit_kernel": {"kernel": f"hsrq::k_crit<{nbv}>", "ms_per_step": round(crit_ms / args.steps, 4),
-                        "launches_per_step": crit_launch / args.steps,
-                        "tflops": round(fl["crit"] / (crit_ms / args.steps * 1e-3) / 1e12, 3) if crit_ms else None},
+                              round(fl["update"] / (tile_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)},
+        "path_tflops": round(fl["total"] / (ms * 1e-3) / 1e12, 3),
         "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "converged_fraction": conv,
         "scale_exp_range": [int(E.min()), int(E.max())],
