@@ -272,6 +272,72 @@ def cpu_baseline(c, seconds, cores):
                 sample=f"first {s} of the {len(wr)} shifts (n={H.shape[0]}), {dt:.1f} s wall on {cores} threads")
 
 
+def bench_c4(args):
+    """Batching: the 512 matrices of uneven order (n log-uniform in
+    [64, 2048], 4-64 shifts each, 30% complex pairs) solved together, the
+    tile size chosen by the library's autotuner, each solve one replay of the
+    captured launch sequence.  One step = one solve of all 512 problems."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05063_amd import Solver
+    from workloads import generators as g
+
+    probs_h = g.config_c4()
+    dev = torch.device("cuda:0")
+
+    def todev(A):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)).to(dev).t()
+
+    Hs = [todev(p["H"]) for p in probs_h]
+    Bs = [todev(p["B"]) for p in probs_h]
+    ncols = sum(B.shape[1] for B in Bs)
+    nshift = sum(len(p["wr"]) for p in probs_h)
+    solver = Solver(0)
+
+    def problems():
+        return [dict(H=H, wr=p["wr"], wi=p["wi"], X=B.clone()) for H, B, p in zip(Hs, Bs, probs_h)]
+
+    best, tune_ms = solver.autotune(problems(), precision=args.precision)
+    sets = [problems() for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.warmup):
+        solver.batched(sets[k], precision=args.precision, graph=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = None
+    for k in range(args.steps):
+        outs = solver.batched(sets[args.warmup + k], precision=args.precision, graph=1)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    conv = float(np.mean(np.concatenate([o[2].cpu().numpy() == 0 for o in outs])))
+    # the same solves launched kernel by kernel, for comparison
+    sets = [problems() for _ in range(args.steps + 1)]
+    solver.batched(sets[0], precision=args.precision, graph=-1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        solver.batched(sets[1 + k], precision=args.precision, graph=-1)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    line = {
+        "metric": "eigenvectors/s (batching: 512 matrices of uneven order)",
+        "value": round(ncols / (ms * 1e-3), 2), "unit": "eigenvectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": "512 random unreduced Hessenberg matrices, n log-uniform in [64, 2048], "
+                               "4-64 host-eigenvalue shifts each (30% complex pairs), all-ones starts",
+                   "matrices": len(probs_h), "sum_n": int(sum(p["H"].shape[0] for p in probs_h)),
+                   "shifts": nshift, "columns": ncols, "precision": args.precision,
+                   "autotuned_nb": best, "autotune_ms": tune_ms, "graph": True},
+        "shifts_per_s": round(nshift / (ms * 1e-3), 2),
+        "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
+        "converged_fraction": conv,
+    }
+    solver.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +347,9 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
+                    help="c3: the headline single-matrix solve; c4: 512 matrices of uneven order in one "
+                         "graph launch (batching)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -295,6 +364,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "c4":
+        bench_c4(args)
         return
 
     import numpy as np

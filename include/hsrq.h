@@ -67,20 +67,30 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
 /*
  * Options.  Zero-initialised options select the defaults.
  *   nb            tile size b_r of Sec. 3.2 (rows and columns of an H tile):
- *                 0 = autotuned; otherwise 32 or 64.
- *   cols_per_block shifts-per-block b_c as columns: 0 = default (64).
+ *                 64 or 128; 0 = the choice of hsrq_autotune for this problem
+ *                 set if it ran on the handle, else 128 when the largest
+ *                 order is >= 2048 and 64 otherwise.
+ *   cols_per_block reserved (shift blocks are fixed by the kernels: 64
+ *                 columns per far-tile block, 16 per critical block).
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
  *                 matrix cores, then an FP64 residual check per shift with a
  *                 fall back to the all-FP64 solve for shifts that fail it.
  *   residual      1 = also compute the FP64 normalised residual
  *                 ||H y - lambda y||_2 / (||H||_F ||y||_2) into resid[].
+ *   graph         1 = replay the launch sequence as a HIP graph (captured on
+ *                 the first call with the same plan shape, workspace and
+ *                 residual option; up to 8 cached per handle); -1 = launch
+ *                 kernel by kernel; 0 = default (graph for batched calls,
+ *                 kernel by kernel for single calls).  Profiling forces
+ *                 kernel-by-kernel launches.
  */
 typedef struct {
     int nb;
     int cols_per_block;
     int precision;
     int residual;
-    int reserved[4];
+    int graph;
+    int reserved[3];
 } hsrq_opts_t;
 
 /* One problem of a batched call.  H, X, scale_exp, scale_mant, info and
@@ -156,12 +166,30 @@ int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t
 /*
  * Many independent problems of uneven order in one launch sequence: every
  * tile-column step of every problem runs in the same kernel launch as the
- * steps of the others, and the whole sequence is one graph launch.
+ * steps of the others (one tile size for the whole set), and by default the
+ * whole sequence is replayed as one HIP graph launch (opts->graph).
  * problems: host array of count descriptors (device data pointers inside).
  * Returns HSRQ_ERR_ARG if any descriptor is invalid.
  */
 int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
                         void* work, size_t work_bytes, const hsrq_opts_t* opts);
+
+/*
+ * Autotuner (tile size b_r).  Runs the solve of the given problem set once
+ * per candidate tile size (64, 128) that fits the workspace, timed with HIP
+ * events on the handle's stream, and records the fastest for this problem
+ * set (keyed by the orders and column counts of its problems) in the handle:
+ * later calls with opts->nb == 0 on a problem set of the same shape use it.
+ * The caller's X, residuals and starting vectors are left untouched;
+ * scale_exp, scale_mant and info receive the results of a candidate run.
+ * Synchronises the handle's stream.  *best_nb (host) receives the choice;
+ * ms (host, length 2, may be NULL) the measured milliseconds per candidate
+ * (0 for a candidate that did not fit).  work as for hsrq_dhsrq3_batched,
+ * sized with opts->nb == 0; opts (may be NULL) as for the solve (its nb and
+ * graph fields are ignored).  Returns HSRQ_ERR_WORKSPACE if no candidate fits.
+ */
+int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work, size_t work_bytes,
+                  const hsrq_opts_t* opts, int* best_nb, double* ms);
 
 /*
  * Debug/parity view of the workspace after a single-problem call: device

@@ -24,14 +24,14 @@ INFO_OK, INFO_NOT_CONVERGED, INFO_SINGULAR, INFO_NONFINITE, INFO_REDUCED = 0, 1,
 EXPORTED = [
     "hsrq_create", "hsrq_destroy", "hsrq_set_stream", "hsrq_workspace_size", "hsrq_dhsrq3",
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
-    "hsrq_profile_enable", "hsrq_profile_read",
+    "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune",
 ]
 KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
 
 class HsrqOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("cols_per_block", ctypes.c_int), ("precision", ctypes.c_int),
-                ("residual", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("residual", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class HsrqProblem(ctypes.Structure):
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_debug_view.argtypes = [vp, i, i, vp, P(HsrqOpts), vp, P(vp), P(vp), P(vp), P(vp), P(i), P(i), vp]
     lib.hsrq_profile_enable.argtypes = [vp, i]
     lib.hsrq_profile_read.argtypes = [vp, i, vp, vp]
+    lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), vp]
     for f in EXPORTED:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -82,11 +83,12 @@ def _check(st, what):
         raise RuntimeError(f"{what} failed with status {st}")
 
 
-def _opts(nb=0, precision=0, residual=False):
+def _opts(nb=0, precision=0, residual=False, graph=0):
     o = HsrqOpts()
     o.nb = int(nb or 0)
     o.precision = int(precision)
     o.residual = 1 if residual else 0
+    o.graph = int(graph)
     return o
 
 
@@ -189,9 +191,7 @@ class Solver:
         E, mu, info, res = self.dhsrq3(H, wr, wi, Y, **kw)
         return Y, E, mu, info, res
 
-    def batched(self, problems, nb=0, precision=0, residual=False, stream=None):
-        """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
-        solved in place).  Returns a list of (E, mu, info, resid)."""
+    def _problem_array(self, problems, residual):
         torch = self.torch
         count = len(problems)
         arr = (HsrqProblem * max(count, 1))()
@@ -215,7 +215,16 @@ class Solver:
             a.X, a.ldx = X.data_ptr(), (X.stride(1) if X.shape[1] > 1 else Hc.shape[0])
             a.scale_exp, a.scale_mant, a.info = E.data_ptr(), mu.data_ptr(), info.data_ptr()
             a.resid = res.data_ptr() if res is not None else None
-        o = _opts(nb, precision, residual)
+        return arr, keep, outs
+
+    def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None):
+        """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
+        solved in place).  Returns a list of (E, mu, info, resid).  graph: 1
+        replay as a HIP graph, -1 launch kernel by kernel, 0 library default
+        (graph)."""
+        count = len(problems)
+        arr, keep, outs = self._problem_array(problems, residual)
+        o = _opts(nb, precision, residual, graph)
         need = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
                "hsrq_workspace_size_batched")
@@ -225,6 +234,24 @@ class Solver:
                "hsrq_dhsrq3_batched")
         self._keep = keep
         return outs
+
+    def autotune(self, problems, precision=0, stream=None):
+        """Times each tile size on this problem set and records the fastest in
+        the handle (used by later calls with nb=0).  Returns (best_nb,
+        {nb: ms}).  The problems' X are not modified."""
+        count = len(problems)
+        arr, keep, outs = self._problem_array(problems, False)
+        o = _opts(0, precision)
+        need = ctypes.c_size_t()
+        _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
+               "hsrq_workspace_size_batched")
+        wp, wb = self.workspace(need.value)
+        self._stream(stream)
+        best = ctypes.c_int()
+        ms = np.zeros(2)
+        _check(self.lib.hsrq_autotune(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o),
+                                      ctypes.byref(best), ms.ctypes.data_as(ctypes.c_void_p)), "hsrq_autotune")
+        return best.value, {64: float(ms[0]), 128: float(ms[1])}
 
     def profile(self, on=True):
         _check(self.lib.hsrq_profile_enable(self.h, 1 if on else 0), "hsrq_profile_enable")

@@ -45,6 +45,26 @@ struct hsrq_handle_s {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  // graph replay: a capture stream and a small cache of instantiated launch
+  // sequences, each with two pinned staging buffers used alternately
+  hipStream_t cap = nullptr;
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    void* staging = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  struct GraphEntry {
+    uint64_t key = 0;
+    uint64_t stamp = 0;
+    size_t head_bytes = 0;
+    GraphSlot slot[2];
+    int next = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t stamp = 0;
+  // autotuner results: problem-set signature -> tile size
+  std::vector<std::pair<uint64_t, int>> tuned;
 };
 
 namespace {
@@ -96,9 +116,52 @@ Layout make_layout(int m, const double* wr, const double* wi) {
 constexpr int kCrit = 16;   // columns of a critical task
 constexpr int kChunk = 128;  // rows per chunk of the final scan
 
-int choose_nb(int n, const hsrq_opts_t* o) {
+constexpr int kNbCandidates[2] = {64, 128};
+
+// FNV-1a over 64-bit words
+struct Sig {
+  uint64_t v = 1469598103934665603ull;
+  void add(uint64_t x) {
+    for (int b = 0; b < 8; ++b) {
+      v ^= (x >> (8 * b)) & 0xff;
+      v *= 1099511628211ull;
+    }
+  }
+};
+
+int count_cols(int m, const double* wi) {
+  int c = 0;
+  for (int l = 0; l < m; ++l) c += (wi[l] != 0.0) ? 2 : 1;
+  return c;
+}
+
+// the autotuner's key: orders and column counts of the problem set
+uint64_t problem_signature(int count, const hsrq_problem_t* probs) {
+  Sig g;
+  g.add((uint64_t)count);
+  for (int p = 0; p < count; ++p) {
+    g.add((uint64_t)probs[p].n);
+    g.add((uint64_t)(probs[p].m > 0 ? count_cols(probs[p].m, probs[p].wi) : 0));
+  }
+  return g.v;
+}
+
+int heuristic_nb(int count, const hsrq_problem_t* probs) {
+  int nmax = 0;
+  for (int p = 0; p < count; ++p) nmax = std::max(nmax, probs[p].n);
+  return nmax >= 2048 ? 128 : 64;
+}
+
+// tile size: explicit option, else the autotuner's choice for this problem
+// set, else a size rule
+int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
   if (o && (o->nb == 64 || o->nb == 128)) return o->nb;
-  return n >= 2048 ? 128 : 64;
+  if (h && !h->tuned.empty()) {
+    const uint64_t key = problem_signature(count, probs);
+    for (auto& e : h->tuned)
+      if (e.first == key) return e.second;
+  }
+  return heuristic_nb(count, probs);
 }
 
 struct ProbPlan {
@@ -123,10 +186,8 @@ struct Plan {
 };
 
 // Carve the workspace and build every host-side table.
-void build_plan(Plan& P, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
-  int nmax = 0;
-  for (int p = 0; p < count; ++p) nmax = std::max(nmax, probs[p].n);
-  P.nb = choose_nb(nmax, o);
+void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) {
+  P.nb = nb_choice;
   const int nb = P.nb;
   P.pp.resize(count);
   int Tmax = 0;
@@ -289,17 +350,11 @@ T* at(void* base, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
-int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, size_t work_bytes,
-        const hsrq_opts_t* o) {
-  Plan P;
-  build_plan(P, count, probs, o);
-  if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
-    return HSRQ_ERR_WORKSPACE;
-  int st = ensure_staging(h, P.head_bytes);
-  if (st) return st;
-  char* hb = static_cast<char*>(h->staging);
+// Writes the plan's head region (descriptors, task and block tables, column
+// metadata) into the host image hb.
+void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* work, const hsrq_opts_t* o,
+                  char* hb) {
   std::memset(hb, 0, P.head_bytes);
-  // descriptors
   std::vector<ProbDesc> descs(count);
   for (int p = 0; p < count; ++p) {
     const ProbPlan& q = P.pp[p];
@@ -343,7 +398,6 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
     d.Mu = pr.scale_mant;
     d.Iu = pr.info;
     d.Ru = pr.resid;
-    // metadata into the staging image
     double* md = reinterpret_cast<double*>(hb + q.o_meta_d);
     int32_t* mi = reinterpret_cast<int32_t*>(hb + q.o_meta_i);
     for (int c = 0; c < q.ncols; ++c) {
@@ -362,30 +416,40 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
   if (!P.blk_cols.empty()) std::memcpy(hb + P.o_bcols, P.blk_cols.data(), sizeof(int2) * P.blk_cols.size());
   if (!P.blk_init.empty()) std::memcpy(hb + P.o_binit, P.blk_init.data(), sizeof(int4) * P.blk_init.size());
   if (!P.blk_out.empty()) std::memcpy(hb + P.o_bout, P.blk_out.data(), sizeof(int4) * P.blk_out.size());
+}
 
-  hipStream_t s = h->stream;
-  if (hipMemcpyAsync(work, hb, P.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
-  if (hipEventRecord(h->staging_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
-  h->staging_pending = true;
-  if (P.blk_cols.empty()) return HSRQ_OK;
-
-  const ProbDesc* dd = at<ProbDesc>(work, P.o_desc);
-  const Task* dt = at<Task>(work, P.o_tasks);
-  {
-    ProfScope ps(h, HSRQ_K_PREP);
-    launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
-    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, s);
-  }
-  { ProfScope ps(h, HSRQ_K_INIT); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
-  // steps: critical tasks on the handle's stream, far tasks on the second
-  // stream; step t of either kind waits for both kinds of step t-1
-  const int T = (int)P.coff.size();
+int ensure_sync_events(hsrq_handle_t h, int T) {
   if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
   while ((int)h->sync_ev.size() < 2 * T + 2) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return HSRQ_ERR_HIP;
     h->sync_ev.push_back(e);
   }
+  return HSRQ_OK;
+}
+
+// Enqueues the whole solve on stream s (and the handle's second stream for
+// the far-tile kernels): head copy from the host image hb, then every kernel.
+// write_out = false leaves the caller's X and residuals untouched (tuning).
+// staging_ev, if given, is recorded right after the head copy.
+int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* hb, hipStream_t s, bool want_res,
+            bool write_out, bool prof, hipEvent_t staging_ev) {
+  if (hipMemcpyAsync(work, hb, P.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
+  if (staging_ev && hipEventRecord(staging_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
+  if (P.blk_cols.empty()) return HSRQ_OK;
+  const bool saved = h->prof;
+  h->prof = prof;  // ProfScope reads the flag
+  const ProbDesc* dd = at<ProbDesc>(work, P.o_desc);
+  const Task* dt = at<Task>(work, P.o_tasks);
+  {
+    ProfScope ps(h, HSRQ_K_PREP, s);
+    launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
+    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, s);
+  }
+  { ProfScope ps(h, HSRQ_K_INIT, s); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
+  // steps: critical tasks on s, far tasks on the second stream; step t of
+  // either kind waits for both kinds of step t-1
+  const int T = (int)P.coff.size();
   hipStream_t a = h->aux;
   hipEvent_t* ev = h->sync_ev.data();
   // ev[2t]: critical step t done; ev[2t+1]: far step t done; ev[2T]: fork
@@ -407,25 +471,173 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
     hipEventRecord(ev[2 * t], s);
     hipEventRecord(ev[2 * t + 1], a);
   }
-  if (T > 0) hipStreamWaitEvent(s, ev[2 * (T - 1) + 1], 0);
+  // join: the second stream's last step (or the fork, with no steps)
+  hipStreamWaitEvent(s, T > 0 ? ev[2 * (T - 1) + 1] : ev[2 * T], 0);
+  if (T == 0) {
+    hipEventRecord(ev[2 * T + 1], a);
+    hipStreamWaitEvent(s, ev[2 * T + 1], 0);
+  }
   {
-    ProfScope ps(h, HSRQ_K_FINAL);
+    ProfScope ps(h, HSRQ_K_FINAL, s);
     launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), at<int4>(work, P.o_bfin),
                  (int)P.blk_fin.size(), s);
   }
-  bool want_res = o && o->residual;
-  if (want_res) {
-    for (int p = 0; p < count; ++p)
-      if (!probs[p].resid) want_res = false;
-  }
-  if (want_res) {
-    ProfScope ps(h, HSRQ_K_RESID);
+  if (write_out && want_res) {
+    ProfScope ps(h, HSRQ_K_RESID, s);
     launch_resid(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), at<int2>(work, P.o_bcols),
                  (int)P.blk_cols.size(), s);
   }
-  { ProfScope ps(h, HSRQ_K_OUTPUT); launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s); }
+  if (write_out) {
+    ProfScope ps(h, HSRQ_K_OUTPUT, s);
+    launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
+  }
+  h->prof = saved;
   if (hipGetLastError() != hipSuccess) return HSRQ_ERR_HIP;
   return HSRQ_OK;
+}
+
+// key of an instantiated launch sequence: everything the captured launches
+// depend on (grid sizes, offsets into the workspace, the workspace itself);
+// the descriptors and tables are re-copied from the staging image per replay
+uint64_t plan_signature(const Plan& P, int count, void* work, bool want_res) {
+  Sig g;
+  g.add((uint64_t)P.nb);
+  g.add((uint64_t)count);
+  g.add((uint64_t)reinterpret_cast<uintptr_t>(work));
+  g.add((uint64_t)want_res);
+  g.add((uint64_t)P.head_bytes);
+  g.add((uint64_t)P.total_bytes);
+  g.add((uint64_t)P.zero_count);
+  g.add((uint64_t)P.o_zero_all);
+  for (size_t v : {P.o_desc, P.o_tasks, P.o_bprep, P.o_bcols, P.o_binit, P.o_bout, P.o_bfin}) g.add(v);
+  for (size_t v : {P.tasks.size(), P.blk_cols.size(), P.blk_prep.size(), P.blk_init.size(), P.blk_out.size(),
+                   P.blk_fin.size(), P.coff.size()})
+    g.add(v);
+  for (size_t t = 0; t < P.coff.size(); ++t) {
+    g.add((uint64_t)P.coff[t]);
+    g.add((uint64_t)P.ccnt[t]);
+    g.add((uint64_t)P.foff[t]);
+    g.add((uint64_t)P.fcnt[t]);
+  }
+  return g.v;
+}
+
+void release_graph(hsrq_handle_s::GraphEntry& e) {
+  for (auto& sl : e.slot) {
+    if (sl.pending) hipEventSynchronize(sl.done);
+    if (sl.exec) hipGraphExecDestroy(sl.exec);
+    if (sl.staging) hipHostFree(sl.staging);
+    if (sl.done) hipEventDestroy(sl.done);
+    sl = hsrq_handle_s::GraphSlot();
+  }
+}
+
+constexpr size_t kGraphCache = 8;
+
+// Replays (capturing on first use) the launch sequence of plan P on stream s.
+int run_graph(hsrq_handle_t h, const Plan& P, int count, const hsrq_problem_t* probs, void* work,
+              const hsrq_opts_t* o, bool want_res, hipStream_t s) {
+  const uint64_t key = plan_signature(P, count, work, want_res);
+  hsrq_handle_s::GraphEntry* e = nullptr;
+  for (auto& x : h->graphs)
+    if (x.key == key) e = &x;
+  if (!e) {
+    if (h->graphs.size() >= kGraphCache) {  // evict the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < h->graphs.size(); ++i)
+        if (h->graphs[i].stamp < h->graphs[lru].stamp) lru = i;
+      release_graph(h->graphs[lru]);
+      h->graphs.erase(h->graphs.begin() + lru);
+    }
+    h->graphs.emplace_back();
+    e = &h->graphs.back();
+    e->key = key;
+    e->head_bytes = P.head_bytes;
+  }
+  e->stamp = ++h->stamp;
+  auto& sl = e->slot[e->next];
+  e->next ^= 1;
+  if (sl.pending) {
+    if (hipEventSynchronize(sl.done) != hipSuccess) return HSRQ_ERR_HIP;
+    sl.pending = false;
+  }
+  if (!sl.staging) {
+    if (hipHostMalloc(&sl.staging, std::max<size_t>(P.head_bytes, 256), hipHostMallocDefault) != hipSuccess) {
+      sl.staging = nullptr;
+      return HSRQ_ERR_ALLOC;
+    }
+    if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) return HSRQ_ERR_HIP;
+  }
+  fill_staging(P, count, probs, work, o, static_cast<char*>(sl.staging));
+  if (!sl.exec) {
+    if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
+    if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HSRQ_ERR_HIP;
+    int st = enqueue(h, P, count, work, sl.staging, h->cap, want_res, true, false, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap, &g);
+    if (st == HSRQ_OK && (ec != hipSuccess || !g)) st = HSRQ_ERR_HIP;
+    if (st == HSRQ_OK && hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      sl.exec = nullptr;
+      st = HSRQ_ERR_HIP;
+    }
+    if (g) hipGraphDestroy(g);
+    if (st) return st;
+  }
+  if (hipGraphLaunch(sl.exec, s) != hipSuccess) return HSRQ_ERR_HIP;
+  if (hipEventRecord(sl.done, s) != hipSuccess) return HSRQ_ERR_HIP;
+  sl.pending = true;
+  return HSRQ_OK;
+}
+
+bool wants_residual(const hsrq_opts_t* o, int count, const hsrq_problem_t* probs) {
+  if (!(o && o->residual)) return false;
+  for (int p = 0; p < count; ++p)
+    if (!probs[p].resid) return false;
+  return true;
+}
+
+// graph option: 1 = replay, -1 = eager launches, 0 = library default (replay
+// for batched calls); profiling always launches eagerly
+bool use_graph(hsrq_handle_t h, const hsrq_opts_t* o, bool batched) {
+  if (h->prof) return false;
+  const int g = o ? o->graph : 0;
+  return g > 0 || (g == 0 && batched);
+}
+
+int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, size_t work_bytes,
+        const hsrq_opts_t* o, bool batched) {
+  Plan P;
+  build_plan(P, count, probs, choose_nb(h, count, probs, o));
+  if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
+    return HSRQ_ERR_WORKSPACE;
+  const bool want_res = wants_residual(o, count, probs);
+  int st = ensure_sync_events(h, (int)P.coff.size());
+  if (st) return st;
+  hipStream_t s = h->stream;
+  if (use_graph(h, o, batched)) return run_graph(h, P, count, probs, work, o, want_res, s);
+  st = ensure_staging(h, P.head_bytes);
+  if (st) return st;
+  fill_staging(P, count, probs, work, o, static_cast<char*>(h->staging));
+  st = enqueue(h, P, count, work, h->staging, s, want_res, true, h->prof, h->staging_ev);
+  h->staging_pending = true;
+  return st;
+}
+
+// bytes of workspace for any tile size the library may pick (nb = 0)
+size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
+  size_t b = 0;
+  if (o && (o->nb == 64 || o->nb == 128)) {
+    Plan P;
+    build_plan(P, count, probs, o->nb);
+    return P.total_bytes;
+  }
+  for (int nb : kNbCandidates) {
+    Plan P;
+    build_plan(P, count, probs, nb);
+    b = std::max(b, P.total_bytes);
+  }
+  (void)h;
+  return b;
 }
 
 int check_problem(const hsrq_problem_t& p) {
@@ -499,6 +711,9 @@ int hsrq_destroy(hsrq_handle_t h) {
     h->ev_pool.push_back(u.second.first);
     h->ev_pool.push_back(u.second.second);
   }
+  for (auto& e : h->graphs) release_graph(e);
+  h->graphs.clear();
+  if (h->cap) hipStreamDestroy(h->cap);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
   if (h->aux) {
@@ -522,9 +737,7 @@ int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t
   if (!h || count < 0 || (count > 0 && !problems) || !bytes) return HSRQ_ERR_ARG;
   for (int p = 0; p < count; ++p)
     if (problems[p].n < 1 || problems[p].m < 0 || (problems[p].m > 0 && !problems[p].wi)) return HSRQ_ERR_ARG;
-  Plan P;
-  build_plan(P, count, problems, opts);
-  *bytes = P.total_bytes;
+  *bytes = plan_bytes(h, count, problems, opts);
   return HSRQ_OK;
 }
 
@@ -538,9 +751,7 @@ int hsrq_workspace_size(hsrq_handle_t h, int n, int m, const double* wi, const h
   std::vector<double> wr(m > 0 ? m : 1, 0.0);
   hsrq_problem_t p{};
   p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;
-  Plan P;
-  build_plan(P, 1, &p, opts);
-  *bytes = P.total_bytes;
+  *bytes = plan_bytes(h, 1, &p, opts);
   return HSRQ_OK;
 }
 
@@ -553,7 +764,7 @@ int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh, int m, const d
   if (st) return st;
   if (!work) return -14;
   if (m == 0) return HSRQ_OK;
-  return run(h, 1, &p, work, work_bytes, opts);
+  return run(h, 1, &p, work, work_bytes, opts, false);
 }
 
 int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work,
@@ -562,7 +773,65 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
   for (int p = 0; p < count; ++p)
     if (check_problem(problems[p])) return HSRQ_ERR_ARG;
   if (count == 0) return HSRQ_OK;
-  return run(h, count, problems, work, work_bytes, opts);
+  return run(h, count, problems, work, work_bytes, opts, true);
+}
+
+int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work, size_t work_bytes,
+                  const hsrq_opts_t* opts, int* best_nb, double* ms) {
+  if (!h || count < 1 || !problems || !best_nb || !work) return HSRQ_ERR_ARG;
+  for (int p = 0; p < count; ++p)
+    if (check_problem(problems[p])) return HSRQ_ERR_ARG;
+  hsrq_opts_t o{};
+  if (opts) o = *opts;
+  o.graph = -1;
+  const bool want_res = false;
+  hipStream_t s = h->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HSRQ_ERR_HIP;
+  int best = 0;
+  double best_ms = 0.0;
+  int st = HSRQ_OK;
+  for (int c = 0; c < 2 && st == HSRQ_OK; ++c) {
+    const int nb = kNbCandidates[c];
+    if (ms) ms[c] = 0.0;
+    Plan P;
+    build_plan(P, count, problems, nb);
+    if (work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1))) continue;
+    if ((st = ensure_sync_events(h, (int)P.coff.size()))) break;
+    float t_best = 0.f;
+    for (int rep = 0; rep < 3 && st == HSRQ_OK; ++rep) {  // first run warms up
+      if ((st = ensure_staging(h, P.head_bytes))) break;
+      fill_staging(P, count, problems, work, &o, static_cast<char*>(h->staging));
+      if (hipEventRecord(e0, s) != hipSuccess) st = HSRQ_ERR_HIP;
+      if (st == HSRQ_OK) st = enqueue(h, P, count, work, h->staging, s, want_res, false, false, h->staging_ev);
+      h->staging_pending = true;
+      if (st == HSRQ_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        st = HSRQ_ERR_HIP;
+      float t = 0.f;
+      if (st == HSRQ_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) st = HSRQ_ERR_HIP;
+      if (st == HSRQ_OK && rep > 0 && (rep == 1 || t < t_best)) t_best = t;
+    }
+    if (st) break;
+    if (ms) ms[c] = t_best;
+    if (best == 0 || t_best < best_ms) {
+      best = nb;
+      best_ms = t_best;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  if (best == 0) return HSRQ_ERR_WORKSPACE;
+  const uint64_t key = problem_signature(count, problems);
+  bool found = false;
+  for (auto& e : h->tuned)
+    if (e.first == key) {
+      e.second = best;
+      found = true;
+    }
+  if (!found) h->tuned.emplace_back(key, best);
+  *best_nb = best;
+  return HSRQ_OK;
 }
 
 int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts, void* work,
@@ -573,7 +842,7 @@ int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_
   hsrq_problem_t p{};
   p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;
   Plan P;
-  build_plan(P, 1, &p, opts);
+  build_plan(P, 1, &p, choose_nb(h, 1, &p, opts));
   const ProbPlan& q = P.pp[0];
   if (C) *C = at<double>(work, q.o_C);
   if (S) *S = at<double>(work, q.o_S);
