@@ -272,11 +272,60 @@ def cpu_baseline(c, seconds, cores):
                 sample=f"first {s} of the {len(wr)} shifts (n={H.shape[0]}), {dt:.1f} s wall on {cores} threads")
 
 
+def error_vs_reference(probs_h, probs_d, outs, cores):
+    """Per-result error of a GPU solve against the plain CPU reference (every
+    shift of every problem): 1 - |cos| of the directions, exponent mismatches
+    (binade straddles excepted), relative mantissa difference."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    O.build()
+
+    def one(b):
+        pr = probs_h[b]
+        return O.batch(pr["H"], pr["wr"], pr["wi"], pr["B"], nthreads=1)
+
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        refs = list(ex.map(one, range(len(probs_h))))
+    dir_err, mu_err, e_mis, straddle = [], [], 0, 0
+    for pr, pd, (E, mu, info, _), (Yo, Eo, muo, infoo) in zip(probs_h, probs_d, outs, refs):
+        Yg = pd["X"].t().contiguous().cpu().numpy().T
+        E, mu = E.cpu().numpy(), mu.cpu().numpy()
+        cols, _ = O.columns_of(pr["wi"])
+        for l in range(len(pr["wr"])):
+            c = cols[l]
+            if pr["wi"][l] != 0.0:
+                yg = Yg[:, c] + 1j * Yg[:, c + 1]
+                yo = Yo[:, c] + 1j * Yo[:, c + 1]
+            else:
+                yg, yo = Yg[:, c], Yo[:, c]
+            d = abs(np.vdot(yg, yo)) / (np.linalg.norm(yg) * np.linalg.norm(yo))
+            dir_err.append(max(0.0, 1.0 - d))
+            if E[l] != Eo[l]:
+                lg = Eo[l] + np.log2(muo[l])
+                if abs(E[l] - Eo[l]) == 1 and abs(lg - round(lg)) < 1e-4:
+                    straddle += 1
+                else:
+                    e_mis += 1
+            else:
+                mu_err.append(abs(mu[l] - muo[l]) / muo[l])
+    dir_err = np.array(dir_err)
+    return {"results": int(dir_err.size), "max_1_minus_cos": float(dir_err.max()),
+            "p99_1_minus_cos": float(np.quantile(dir_err, 0.99)),
+            "max_rel_mantissa_diff": float(max(mu_err) if mu_err else 0.0),
+            "exponent_mismatches": e_mis, "exponent_binade_straddles": straddle}
+
+
 def bench_c4(args):
     """Batching: the 512 matrices of uneven order (n log-uniform in
     [64, 2048], 4-64 shifts each, 30% complex pairs) solved together, the
     tile size chosen by the library's autotuner, each solve one replay of the
-    captured launch sequence.  One step = one solve of all 512 problems."""
+    captured launch sequence (precision 0).  With --precision 1 the
+    mixed-precision solve (FP32 tile products, FP64 residual check, FP64
+    fallback; not graph-replayed because of its host check) is timed, and
+    every result's error against the CPU reference is reported.  One step =
+    one solve of all 512 problems."""
     import numpy as np
     import torch
 
@@ -299,27 +348,24 @@ def bench_c4(args):
         return [dict(H=H, wr=p["wr"], wi=p["wi"], X=B.clone()) for H, B, p in zip(Hs, Bs, probs_h)]
 
     best, tune_ms = solver.autotune(problems(), precision=args.precision)
-    sets = [problems() for _ in range(args.warmup + args.steps)]
-    torch.cuda.synchronize()
-    for k in range(args.warmup):
-        solver.batched(sets[k], precision=args.precision, graph=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = None
-    for k in range(args.steps):
-        outs = solver.batched(sets[args.warmup + k], precision=args.precision, graph=1)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    def timed(graph):
+        sets = [problems() for _ in range(args.warmup + args.steps)]
+        torch.cuda.synchronize()
+        for k in range(args.warmup):
+            solver.batched(sets[k], precision=args.precision, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = None
+        for k in range(args.steps):
+            outs = solver.batched(sets[args.warmup + k], precision=args.precision, graph=graph)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, sets[-1], outs
+
+    ms, last_set, outs = timed(1)
+    fallback = solver.fallback_count() if args.precision == 1 else 0
     conv = float(np.mean(np.concatenate([o[2].cpu().numpy() == 0 for o in outs])))
-    # the same solves launched kernel by kernel, for comparison
-    sets = [problems() for _ in range(args.steps + 1)]
-    solver.batched(sets[0], precision=args.precision, graph=-1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        solver.batched(sets[1 + k], precision=args.precision, graph=-1)
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_eager, _, _ = timed(-1)
     line = {
         "metric": "eigenvectors/s (batching: 512 matrices of uneven order)",
         "value": round(ncols / (ms * 1e-3), 2), "unit": "eigenvectors/s", "n_gpus": 1, "steps": args.steps,
@@ -329,11 +375,14 @@ def bench_c4(args):
                                "4-64 host-eigenvalue shifts each (30% complex pairs), all-ones starts",
                    "matrices": len(probs_h), "sum_n": int(sum(p["H"].shape[0] for p in probs_h)),
                    "shifts": nshift, "columns": ncols, "precision": args.precision,
-                   "autotuned_nb": best, "autotune_ms": tune_ms, "graph": True},
+                   "autotuned_nb": best, "autotune_ms": tune_ms, "graph": args.precision == 0},
         "shifts_per_s": round(nshift / (ms * 1e-3), 2),
         "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
         "converged_fraction": conv,
     }
+    if args.precision == 1:
+        line["fallback_shifts"] = fallback
+        line["error_vs_reference"] = error_vs_reference(probs_h, last_set, outs, len(os.sched_getaffinity(0)))
     solver.close()
     print(json.dumps(line), flush=True)
 
@@ -447,6 +496,8 @@ def main():
         "converged_fraction": conv,
         "scale_exp_range": [int(E.min()), int(E.max())],
     }
+    if args.precision == 1:
+        line["fallback_shifts"] = solver.fallback_count()
     if not args.no_cpu_baseline:
         cores = len(os.sched_getaffinity(0))
         line["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, cores)

@@ -175,6 +175,23 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
                         void* work, size_t work_bytes, const hsrq_opts_t* opts);
 
 /*
+ * Mixed precision (opts->precision == 1).  The call runs in three phases on
+ * the handle's stream: (1) the whole solve with the tile-update products in
+ * FP32 on the matrix cores (operands scaled by powers of two into FP32 range,
+ * FP32 accumulation over a tile; rotations, scale factors, small solves and
+ * normalisation stay FP64) and the FP64 normalised residual of every shift;
+ * (2) one host synchronisation; a shift passes when it converged and its
+ * residual is at most 10 n eps (eps = 2^-52); (3) the shifts that fail are
+ * solved again from their starting vectors entirely in FP64 and their outputs
+ * replace the first pass's.  Shifts flagged singular (2) or with invalid input
+ * (3, 4) are final after phase 1.  The call therefore returns only after
+ * phase 2; phase 3 is asynchronous.  Workspace: query with the same opts.
+ * hsrq_fallback_count writes the number of shifts re-solved by the last such
+ * call on the handle.
+ */
+int hsrq_fallback_count(hsrq_handle_t h, int64_t* count);
+
+/*
  * Autotuner (tile size b_r).  Runs the solve of the given problem set once
  * per candidate tile size (64, 128) that fits the workspace, timed with HIP
  * events on the handle's stream, and records the fastest for this problem

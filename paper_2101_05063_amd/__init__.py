@@ -24,7 +24,7 @@ INFO_OK, INFO_NOT_CONVERGED, INFO_SINGULAR, INFO_NONFINITE, INFO_REDUCED = 0, 1,
 EXPORTED = [
     "hsrq_create", "hsrq_destroy", "hsrq_set_stream", "hsrq_workspace_size", "hsrq_dhsrq3",
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
-    "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune",
+    "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune", "hsrq_fallback_count",
 ]
 KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_profile_enable.argtypes = [vp, i]
     lib.hsrq_profile_read.argtypes = [vp, i, vp, vp]
     lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), vp]
+    lib.hsrq_fallback_count.argtypes = [vp, P(ctypes.c_int64)]
     for f in EXPORTED:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -252,6 +253,12 @@ class Solver:
         _check(self.lib.hsrq_autotune(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o),
                                       ctypes.byref(best), ms.ctypes.data_as(ctypes.c_void_p)), "hsrq_autotune")
         return best.value, {64: float(ms[0]), 128: float(ms[1])}
+
+    def fallback_count(self):
+        """Shifts re-solved in FP64 by the last mixed-precision call."""
+        n = ctypes.c_int64()
+        _check(self.lib.hsrq_fallback_count(self.h, ctypes.byref(n)), "hsrq_fallback_count")
+        return n.value
 
     def profile(self, on=True):
         _check(self.lib.hsrq_profile_enable(self.h, 1 if on else 0), "hsrq_profile_enable")

@@ -54,6 +54,13 @@ struct Task {
   int32_t prob, type, i, L;
 };
 
+// one copy of a gather/scatter list (bytes, a multiple of 4)
+struct CopyEnt {
+  const void* src;
+  void* dst;
+  long long nbytes;
+};
+
 __host__ __device__ inline int tile_end(int n, int N, int nb, int t) { return n - (N - 1 - t) * nb; }
 __host__ __device__ inline int tile_start(int n, int N, int nb, int t) {
   int e = tile_end(n, N, nb, t);

@@ -21,12 +21,13 @@
 namespace hsrq {
 void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_crit(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
-void launch_far(int nb, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
+void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
+void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
 void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
 void launch_fill(double* p, long long cnt, double v, hipStream_t st);
+void launch_copy(const CopyEnt* ents, int count, hipStream_t st);
 }  // namespace hsrq
 
 using namespace hsrq;
@@ -65,6 +66,13 @@ struct hsrq_handle_s {
   uint64_t stamp = 0;
   // autotuner results: problem-set signature -> tile size
   std::vector<std::pair<uint64_t, int>> tuned;
+  // mixed precision: shifts re-solved in FP64 by the last call, and a pinned
+  // buffer for the gather/scatter lists (read by the copy kernel in place)
+  size_t last_fallback = 0;
+  void* lists = nullptr;
+  size_t lists_bytes = 0;
+  hipEvent_t lists_ev = nullptr;
+  bool lists_pending = false;
 };
 
 namespace {
@@ -175,6 +183,7 @@ struct ProbPlan {
 
 struct Plan {
   int nb = 64;
+  int prec = 0;  // 1: FP32 tile-update products
   std::vector<ProbPlan> pp;
   std::vector<Task> tasks;
   std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
@@ -430,10 +439,11 @@ int ensure_sync_events(hsrq_handle_t h, int T) {
 
 // Enqueues the whole solve on stream s (and the handle's second stream for
 // the far-tile kernels): head copy from the host image hb, then every kernel.
-// write_out = false leaves the caller's X and residuals untouched (tuning).
-// staging_ev, if given, is recorded right after the head copy.
-int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* hb, hipStream_t s, bool want_res,
-            bool write_out, bool prof, hipEvent_t staging_ev) {
+// do_output = false leaves the caller's X untouched (tuning, and the first
+// pass of the mixed-precision solve); staging_ev, if given, is recorded right
+// after the head copy.
+int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* hb, hipStream_t s, bool do_resid,
+            bool do_output, bool prof, hipEvent_t staging_ev) {
   if (hipMemcpyAsync(work, hb, P.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
   if (staging_ev && hipEventRecord(staging_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
   if (P.blk_cols.empty()) return HSRQ_OK;
@@ -462,11 +472,11 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s);
-      launch_crit(P.nb, dd, dt + P.coff[t], P.ccnt[t], t, s);
+      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], t, s);
     }
     if (P.fcnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_FAR, a);
-      launch_far(P.nb, dd, dt + P.foff[t], P.fcnt[t], t, a);
+      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], t, a);
     }
     hipEventRecord(ev[2 * t], s);
     hipEventRecord(ev[2 * t + 1], a);
@@ -482,12 +492,12 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), at<int4>(work, P.o_bfin),
                  (int)P.blk_fin.size(), s);
   }
-  if (write_out && want_res) {
+  if (do_resid) {
     ProfScope ps(h, HSRQ_K_RESID, s);
     launch_resid(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), at<int2>(work, P.o_bcols),
                  (int)P.blk_cols.size(), s);
   }
-  if (write_out) {
+  if (do_output) {
     ProfScope ps(h, HSRQ_K_OUTPUT, s);
     launch_output(dd, at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
   }
@@ -604,8 +614,223 @@ bool use_graph(hsrq_handle_t h, const hsrq_opts_t* o, bool batched) {
   return g > 0 || (g == 0 && batched);
 }
 
+// Mixed precision (opts->precision == 1), in three phases:
+//   1. the whole solve with FP32 tile-update products (every rotation, scale
+//      factor, small solve and the normalisation stay FP64), and the FP64
+//      residual ||H y - lambda y||_2 / (||H||_F ||y||_2) of every shift, with
+//      the caller's X (the starting vectors) still untouched;
+//   2. one synchronisation; a shift passes when its residual is at most
+//      10 n eps (eps = 2^-52) and it converged;
+//   3. the starting vectors of the failing shifts are gathered, solved again
+//      all in FP64 (the fallback), and scattered back over the first pass's
+//      results.  Shifts flagged singular or with invalid input are final.
+// Workspace: [first pass | fallback pass | gathered columns | per-shift
+// scalars], each region 256-byte aligned.
+struct MixedLayout {
+  size_t o_pass2 = 0, o_cols = 0, o_scal = 0, total = 0;
+  std::vector<size_t> col_off, res_off;  // per problem, inside the regions
+};
+
+MixedLayout mixed_layout(int count, const hsrq_problem_t* probs, size_t pass_bytes) {
+  MixedLayout L;
+  size_t off = align_up(pass_bytes);
+  L.o_pass2 = off;
+  off = align_up(off + pass_bytes);
+  L.o_cols = off;
+  L.col_off.resize(count);
+  for (int p = 0; p < count; ++p) {
+    L.col_off[p] = off;
+    const int nc = probs[p].m > 0 ? count_cols(probs[p].m, probs[p].wi) : 0;
+    off = align_up(off + sizeof(double) * (size_t)probs[p].n * nc);
+  }
+  L.o_scal = off;
+  L.res_off.resize(count);
+  for (int p = 0; p < count; ++p) {
+    L.res_off[p] = off;  // resid (m doubles), then E (m), info (m), mu (m) of the fallback
+    off = align_up(off + (sizeof(double) * 2 + sizeof(int32_t) * 2) * (size_t)std::max(probs[p].m, 1) + 64);
+  }
+  L.total = off;
+  return L;
+}
+
+int run_mixed(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, size_t work_bytes,
+              const hsrq_opts_t* o) {
+  h->last_fallback = 0;
+  const int nb = choose_nb(h, count, probs, o);
+  Plan P;
+  build_plan(P, count, probs, nb);
+  P.prec = 1;
+  const MixedLayout L = mixed_layout(count, probs, P.total_bytes);
+  if (!work || work_bytes < L.total || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
+    return HSRQ_ERR_WORKSPACE;
+  hipStream_t s = h->stream;
+  int st = ensure_sync_events(h, (int)P.coff.size());
+  if (st) return st;
+  // phase 1: residuals go to the caller's array if given, else to ours
+  std::vector<hsrq_problem_t> q1(probs, probs + count);
+  for (int p = 0; p < count; ++p)
+    if (!q1[p].resid) q1[p].resid = at<double>(work, L.res_off[p]);
+  if ((st = ensure_staging(h, P.head_bytes))) return st;
+  hsrq_opts_t o1 = *o;
+  fill_staging(P, count, q1.data(), work, &o1, static_cast<char*>(h->staging));
+  st = enqueue(h, P, count, work, h->staging, s, true, false, h->prof, h->staging_ev);
+  h->staging_pending = true;
+  if (st) return st;
+  // phase 2: the check
+  std::vector<std::vector<int>> fail(count);
+  size_t nfail = 0;
+  {
+    size_t mt = 0;
+    std::vector<size_t> base(count);
+    for (int p = 0; p < count; ++p) {
+      base[p] = mt;
+      mt += q1[p].m;
+    }
+    std::vector<double> res(std::max<size_t>(mt, 1));
+    std::vector<int32_t> inf(std::max<size_t>(mt, 1));
+    for (int p = 0; p < count; ++p) {
+      const int m = q1[p].m;
+      if (m == 0) continue;
+      if (hipMemcpyAsync(res.data() + base[p], q1[p].resid, sizeof(double) * m, hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipMemcpyAsync(inf.data() + base[p], q1[p].info, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s) !=
+              hipSuccess)
+        return HSRQ_ERR_HIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return HSRQ_ERR_HIP;
+    for (int p = 0; p < count; ++p) {
+      const double tol = 10.0 * q1[p].n * std::ldexp(1.0, -52);
+      for (int l = 0; l < q1[p].m; ++l) {
+        const int32_t in = inf[base[p] + l];
+        const bool final_flag = in == 2 || in == 3 || in == 4;
+        if (!final_flag && (in != 0 || !(res[base[p] + l] <= tol))) fail[p].push_back(l);
+      }
+      nfail += fail[p].size();
+    }
+  }
+  if (nfail == 0) {
+    ProfScope ps(h, HSRQ_K_OUTPUT, s);
+    launch_output(at<ProbDesc>(work, P.o_desc), at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
+    return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
+  }
+  // phase 3: gather the starting vectors of the failing shifts (the caller's
+  // X still holds them), then let the first pass write its output
+  std::vector<hsrq_problem_t> q2;
+  std::vector<int> src;                         // problem of each fallback problem
+  std::vector<std::vector<double>> wr2, wi2;    // host shift lists of the fallback
+  std::vector<std::vector<int>> col2;           // caller column of each gathered column
+  std::vector<CopyEnt> gather, scatter;
+  for (int p = 0; p < count; ++p) {
+    if (fail[p].empty()) continue;
+    const hsrq_problem_t& pr = probs[p];
+    std::vector<int> firstcol(pr.m);
+    for (int l = 0, c = 0; l < pr.m; ++l) {
+      firstcol[l] = c;
+      c += pr.wi[l] != 0.0 ? 2 : 1;
+    }
+    wr2.emplace_back();
+    wi2.emplace_back();
+    col2.emplace_back();
+    double* G = at<double>(work, L.col_off[p]);
+    int g = 0;
+    for (int l : fail[p]) {
+      wr2.back().push_back(pr.wr[l]);
+      wi2.back().push_back(pr.wi[l]);
+      const int w = pr.wi[l] != 0.0 ? 2 : 1;
+      for (int k = 0; k < w; ++k) {
+        col2.back().push_back(firstcol[l] + k);
+        gather.push_back(CopyEnt{pr.X + (size_t)(firstcol[l] + k) * pr.ldx, G + (size_t)g * pr.n,
+                                 (long long)sizeof(double) * pr.n});
+        ++g;
+      }
+    }
+    char* sc = at<char>(work, L.res_off[p]);
+    const size_t mm = (size_t)std::max(pr.m, 1);
+    hsrq_problem_t f{};
+    f.n = pr.n;
+    f.H = pr.H;
+    f.ldh = pr.ldh;
+    f.m = (int)fail[p].size();
+    f.X = G;
+    f.ldx = pr.n;
+    f.resid = reinterpret_cast<double*>(sc);
+    f.scale_exp = reinterpret_cast<int32_t*>(sc + sizeof(double) * mm);
+    f.info = reinterpret_cast<int32_t*>(sc + (sizeof(double) + sizeof(int32_t)) * mm);
+    f.scale_mant = reinterpret_cast<double*>(sc + (sizeof(double) + 2 * sizeof(int32_t)) * mm);
+    q2.push_back(f);
+    src.push_back(p);
+  }
+  for (size_t k = 0; k < q2.size(); ++k) {
+    q2[k].wr = wr2[k].data();
+    q2[k].wi = wi2[k].data();
+  }
+  // scatter list: the fallback's vectors and scalars over the first pass's
+  for (size_t k = 0; k < q2.size(); ++k) {
+    const hsrq_problem_t& pr = probs[src[k]];
+    const hsrq_problem_t& f = q2[k];
+    for (size_t g = 0; g < col2[k].size(); ++g)
+      scatter.push_back(CopyEnt{f.X + g * (size_t)pr.n, pr.X + (size_t)col2[k][g] * pr.ldx,
+                                (long long)sizeof(double) * pr.n});
+    const std::vector<int>& fl = fail[src[k]];
+    for (size_t j = 0; j < fl.size(); ++j) {
+      const int l = fl[j];
+      scatter.push_back(CopyEnt{f.scale_exp + j, pr.scale_exp + l, (long long)sizeof(int32_t)});
+      scatter.push_back(CopyEnt{f.scale_mant + j, pr.scale_mant + l, (long long)sizeof(double)});
+      scatter.push_back(CopyEnt{f.info + j, pr.info + l, (long long)sizeof(int32_t)});
+      if (pr.resid) scatter.push_back(CopyEnt{f.resid + j, pr.resid + l, (long long)sizeof(double)});
+    }
+  }
+  // both lists in one pinned buffer that the copy kernel reads in place
+  {
+    const size_t need = sizeof(CopyEnt) * (gather.size() + scatter.size());
+    if (h->lists_pending) {
+      if (hipEventSynchronize(h->lists_ev) != hipSuccess) return HSRQ_ERR_HIP;
+      h->lists_pending = false;
+    }
+    if (!h->lists_ev && hipEventCreateWithFlags(&h->lists_ev, hipEventDisableTiming) != hipSuccess)
+      return HSRQ_ERR_HIP;
+    if (h->lists_bytes < need) {
+      if (h->lists) hipHostFree(h->lists);
+      h->lists = nullptr;
+      h->lists_bytes = 0;
+      if (hipHostMalloc(&h->lists, need, hipHostMallocDefault) != hipSuccess) {
+        h->lists = nullptr;
+        return HSRQ_ERR_ALLOC;
+      }
+      h->lists_bytes = need;
+    }
+    std::memcpy(h->lists, gather.data(), sizeof(CopyEnt) * gather.size());
+    std::memcpy(static_cast<CopyEnt*>(h->lists) + gather.size(), scatter.data(), sizeof(CopyEnt) * scatter.size());
+  }
+  launch_copy(static_cast<const CopyEnt*>(h->lists), (int)gather.size(), s);
+  {
+    ProfScope ps(h, HSRQ_K_OUTPUT, s);
+    launch_output(at<ProbDesc>(work, P.o_desc), at<int4>(work, P.o_bout), (int)P.blk_out.size(), s);
+  }
+  // the fallback, all FP64, in its own workspace region
+  Plan P2;
+  build_plan(P2, (int)q2.size(), q2.data(), nb);
+  P2.prec = 0;
+  void* w2 = at<char>(work, L.o_pass2);
+  if (P2.total_bytes > P.total_bytes) return HSRQ_ERR_WORKSPACE;
+  if ((st = ensure_sync_events(h, (int)P2.coff.size()))) return st;
+  if ((st = ensure_staging(h, P2.head_bytes))) return st;
+  hsrq_opts_t o2 = *o;
+  o2.precision = 0;
+  fill_staging(P2, (int)q2.size(), q2.data(), w2, &o2, static_cast<char*>(h->staging));
+  st = enqueue(h, P2, (int)q2.size(), w2, h->staging, s, true, true, h->prof, h->staging_ev);
+  h->staging_pending = true;
+  if (st) return st;
+  launch_copy(static_cast<const CopyEnt*>(h->lists) + gather.size(), (int)scatter.size(), s);
+  if (hipEventRecord(h->lists_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
+  h->lists_pending = true;
+  h->last_fallback = nfail;
+  return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
+}
+
 int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, size_t work_bytes,
         const hsrq_opts_t* o, bool batched) {
+  if (o && o->precision == 1) return run_mixed(h, count, probs, work, work_bytes, o);
   Plan P;
   build_plan(P, count, probs, choose_nb(h, count, probs, o));
   if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
@@ -626,15 +851,12 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
 // bytes of workspace for any tile size the library may pick (nb = 0)
 size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
   size_t b = 0;
-  if (o && (o->nb == 64 || o->nb == 128)) {
-    Plan P;
-    build_plan(P, count, probs, o->nb);
-    return P.total_bytes;
-  }
+  const bool mixed = o && o->precision == 1;
   for (int nb : kNbCandidates) {
+    if (o && (o->nb == 64 || o->nb == 128) && nb != o->nb) continue;
     Plan P;
     build_plan(P, count, probs, nb);
-    b = std::max(b, P.total_bytes);
+    b = std::max(b, mixed ? mixed_layout(count, probs, P.total_bytes).total : P.total_bytes);
   }
   (void)h;
   return b;
@@ -680,6 +902,12 @@ int hsrq_profile_enable(hsrq_handle_t h, int on) {
   return HSRQ_OK;
 }
 
+int hsrq_fallback_count(hsrq_handle_t h, int64_t* count) {
+  if (!h || !count) return -1;
+  *count = (int64_t)h->last_fallback;
+  return HSRQ_OK;
+}
+
 int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches) {
   if (!h || nkinds < 0 || (nkinds > 0 && (!ms || !launches))) return -1;
   for (int k = 0; k < nkinds; ++k) {
@@ -713,6 +941,9 @@ int hsrq_destroy(hsrq_handle_t h) {
   }
   for (auto& e : h->graphs) release_graph(e);
   h->graphs.clear();
+  if (h->lists_pending) hipEventSynchronize(h->lists_ev);
+  if (h->lists) hipHostFree(h->lists);
+  if (h->lists_ev) hipEventDestroy(h->lists_ev);
   if (h->cap) hipStreamDestroy(h->cap);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
@@ -796,6 +1027,7 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
     if (ms) ms[c] = 0.0;
     Plan P;
     build_plan(P, count, problems, nb);
+    P.prec = o.precision == 1 ? 1 : 0;
     if (work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1))) continue;
     if ((st = ensure_sync_events(h, (int)P.coff.size()))) break;
     float t_best = 0.f;

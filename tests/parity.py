@@ -27,7 +27,8 @@ def vec(Y, cols, wi, l):
     return Y[:, c] + 1j * Y[:, c + 1] if wi[l] != 0 else Y[:, c]
 
 
-def compare(Yg, Eg, mug, infog, Yo, Eo, muo, infoo, wi, dir_tol=1e-10, sel=None, mu_tol=1e-12):
+def compare(Yg, Eg, mug, infog, Yo, Eo, muo, infoo, wi, dir_tol=1e-10, sel=None, mu_tol=1e-12,
+            straddle_tol=1e-9):
     """Compare per shift; returns dict(straddles=[...]) and raises on failure."""
     from oracle.oracle import columns_of
     cols, _ = columns_of(wi)
@@ -43,7 +44,7 @@ def compare(Yg, Eg, mug, infog, Yo, Eo, muo, infoo, wi, dir_tol=1e-10, sel=None,
         elif Eg[l] != Eo[l]:
             # a straddle: |log2 ||x|| - integer| tiny
             lg = Eo[l] + np.log2(muo[l])
-            assert abs(Eg[l] - Eo[l]) == 1 and abs(lg - round(lg)) < 1e-9, (l, Eg[l], Eo[l], muo[l], mug[l])
+            assert abs(Eg[l] - Eo[l]) == 1 and abs(lg - round(lg)) < straddle_tol, (l, Eg[l], Eo[l], muo[l], mug[l])
             straddles.append(l)
         else:
             assert abs(mug[l] - muo[l]) <= mu_tol * muo[l] + 1e-300, (l, mug[l], muo[l])
