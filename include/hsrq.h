@@ -244,6 +244,49 @@ enum {
 int hsrq_profile_enable(hsrq_handle_t h, int on);
 int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches);
 
+/*
+ * Serving: a request loop with continuous batching (one worker thread per
+ * server, on HIP device `device`).
+ *
+ * hsrq_server_submit queues one problem (H and X device-resident, owned by
+ * the caller and kept alive until its completion is polled; wr and wi are
+ * copied).  Requests are admitted in arrival order while the sum of their
+ * device bytes (workspace, which the server allocates from its own pool, plus
+ * H and X) stays within hbm_budget_bytes.  Every admitted request advances one
+ * tile-column step per tick; a tick is one critical and one far-tile launch
+ * covering every admitted request at whatever step it is, so requests that
+ * arrive while others run join at the next tick.  opts: nb (0 = 128),
+ * precision (0 all FP64; 1 FP32 tile products with the FP64 residual check and
+ * an FP64 re-solve of the failing shifts, see hsrq_fallback_count), residual
+ * (write resid[] when the problem gives it).  Graph replay does not apply.
+ * Returns HSRQ_ERR_BUSY from submit when the request can never fit (its bytes
+ * exceed the budget or its task lists exceed a tick), HSRQ_ERR_ARG for an
+ * invalid problem (n < 1, m < 1, missing pointers) or a stopped server.
+ *
+ * hsrq_server_poll moves up to `max` completion records (host array) out of
+ * the server, waiting up to wait_ms milliseconds when none is ready; *count
+ * receives how many.  Times are seconds on the server's steady clock
+ * (hsrq_server_clock); latency = t_done - t_submit, where t_done is when the
+ * worker observed the request's last kernel complete.  The return value is a
+ * device error that stopped the server, else HSRQ_OK.
+ * hsrq_server_destroy finishes every queued request, then releases the pool.
+ */
+typedef struct hsrq_server_s* hsrq_server_t;
+typedef struct {
+    uint64_t tag;
+    int status;      /* HSRQ_OK or the error that failed the request */
+    int fallback;    /* shifts re-solved in FP64 (precision 1) */
+    double t_submit;
+    double t_start;  /* admitted */
+    double t_done;
+} hsrq_completion_t;
+
+int hsrq_server_create(hsrq_server_t* out, int device, size_t hbm_budget_bytes, const hsrq_opts_t* opts);
+int hsrq_server_submit(hsrq_server_t server, const hsrq_problem_t* problem, uint64_t tag);
+int hsrq_server_poll(hsrq_server_t server, hsrq_completion_t* out, int max, int* count, int wait_ms);
+int hsrq_server_clock(hsrq_server_t server, double* seconds);
+int hsrq_server_destroy(hsrq_server_t server);
+
 #ifdef __cplusplus
 }
 #endif

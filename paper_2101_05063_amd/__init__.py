@@ -25,6 +25,7 @@ EXPORTED = [
     "hsrq_create", "hsrq_destroy", "hsrq_set_stream", "hsrq_workspace_size", "hsrq_dhsrq3",
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
     "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune", "hsrq_fallback_count",
+    "hsrq_server_create", "hsrq_server_submit", "hsrq_server_poll", "hsrq_server_clock", "hsrq_server_destroy",
 ]
 KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
@@ -32,6 +33,11 @@ KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 class HsrqOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("cols_per_block", ctypes.c_int), ("precision", ctypes.c_int),
                 ("residual", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+
+
+class HsrqCompletion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class HsrqProblem(ctypes.Structure):
@@ -67,6 +73,11 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_profile_read.argtypes = [vp, i, vp, vp]
     lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), vp]
     lib.hsrq_fallback_count.argtypes = [vp, P(ctypes.c_int64)]
+    lib.hsrq_server_create.argtypes = [P(vp), i, sz, P(HsrqOpts)]
+    lib.hsrq_server_submit.argtypes = [vp, P(HsrqProblem), ctypes.c_uint64]
+    lib.hsrq_server_poll.argtypes = [vp, P(HsrqCompletion), i, P(i), i]
+    lib.hsrq_server_clock.argtypes = [vp, P(ctypes.c_double)]
+    lib.hsrq_server_destroy.argtypes = [vp]
     for f in EXPORTED:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -296,3 +307,82 @@ class Solver:
             assert off % 8 == 0
             out.append(self._ws[off:off + 8 * n * ld.value].view(torch.float64).view(n, ld.value))
         return dict(C=out[0], S=out[1], PHI=out[2], V=out[3], ld=ld.value, nb=nbo.value, col_of=col_of[:m])
+
+
+class Server:
+    """The library's serving loop (continuous batching under an HBM budget)
+    for torch tensors.  submit() takes device H and X (X column-major, solved
+    in place) and returns the device output tensors; they are valid once
+    poll() has returned the request's tag."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 200 * 10 ** 9, nb: int = 0, precision: int = 0,
+                 residual: bool = False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP library has no CPU fallback")
+        self.torch = torch
+        self.lib = load_library()
+        self.residual = residual
+        h = ctypes.c_void_p()
+        o = _opts(nb, precision, residual)
+        _check(self.lib.hsrq_server_create(ctypes.byref(h), device, int(budget_bytes), ctypes.byref(o)),
+               "hsrq_server_create")
+        self.h = h
+        self._pending = {}
+
+    def submit(self, H, wr, wi, X, tag):
+        """Queue one request; returns (E, mu, info, resid) device tensors.
+        Raises on an invalid request; returns None if it can never fit."""
+        torch = self.torch
+        Hc, ldh = colmajor(H)
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        m = wr.shape[0]
+        dev = Hc.device
+        E = torch.empty(m, dtype=torch.int32, device=dev)
+        mu = torch.empty(m, dtype=torch.float64, device=dev)
+        info = torch.empty(m, dtype=torch.int32, device=dev)
+        res = torch.empty(m, dtype=torch.float64, device=dev) if self.residual else None
+        a = HsrqProblem()
+        a.n, a.H, a.ldh, a.m = Hc.shape[0], Hc.data_ptr(), ldh, m
+        a.wr, a.wi = wr.ctypes.data, wi.ctypes.data
+        a.X, a.ldx = X.data_ptr(), (X.stride(1) if X.shape[1] > 1 else Hc.shape[0])
+        a.scale_exp, a.scale_mant, a.info = E.data_ptr(), mu.data_ptr(), info.data_ptr()
+        a.resid = res.data_ptr() if res is not None else None
+        st = self.lib.hsrq_server_submit(self.h, ctypes.byref(a), int(tag))
+        if st == -1005:
+            return None
+        _check(st, "hsrq_server_submit")
+        out = (E, mu, info, res)
+        self._pending[int(tag)] = (Hc, X, out)
+        return out
+
+    def poll(self, max_count=1024, wait_ms=0):
+        """Completion records (dicts) of finished requests."""
+        buf = (HsrqCompletion * max(1, max_count))()
+        n = ctypes.c_int()
+        _check(self.lib.hsrq_server_poll(self.h, buf, max_count, ctypes.byref(n), int(wait_ms)), "hsrq_server_poll")
+        out = []
+        for k in range(n.value):
+            c = buf[k]
+            self._pending.pop(int(c.tag), None)
+            out.append(dict(tag=int(c.tag), status=c.status, fallback=c.fallback, t_submit=c.t_submit,
+                            t_start=c.t_start, t_done=c.t_done))
+        return out
+
+    def clock(self):
+        t = ctypes.c_double()
+        _check(self.lib.hsrq_server_clock(self.h, ctypes.byref(t)), "hsrq_server_clock")
+        return t.value
+
+    def close(self):
+        if self.h:
+            self.lib.hsrq_server_destroy(self.h)
+            self.h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

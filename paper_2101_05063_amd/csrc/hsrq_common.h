@@ -50,9 +50,15 @@ struct ProbDesc {
   double* Ru;
 };
 
+// one block of a step launch: problem, task type | (step << 8), tile row,
+// column block.  The step travels with the task so that one launch can hold
+// problems at different steps (continuous batching).
 struct Task {
   int32_t prob, type, i, L;
 };
+__host__ __device__ inline int32_t task_code(int type, int step) { return type | (step << 8); }
+__host__ __device__ inline int task_type(int32_t code) { return code & 0xff; }
+__host__ __device__ inline int task_step(int32_t code) { return code >> 8; }
 
 // one copy of a gather/scatter list (bytes, a multiple of 4)
 struct CopyEnt {

@@ -17,77 +17,13 @@
 
 #include "hsrq.h"
 #include "hsrq_common.h"
+#include "hsrq_plan.h"
 
-namespace hsrq {
-void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
-void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
-void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, int t, hipStream_t st);
-void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
-void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
-void launch_fill(double* p, long long cnt, double v, hipStream_t st);
-void launch_copy(const CopyEnt* ents, int count, hipStream_t st);
-}  // namespace hsrq
 
 using namespace hsrq;
 
-struct hsrq_handle_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  void* staging = nullptr;
-  size_t staging_bytes = 0;
-  hipEvent_t staging_ev = nullptr;
-  bool staging_pending = false;
-  // second stream for the far-tile kernels, and fork/join events
-  hipStream_t aux = nullptr;
-  std::vector<hipEvent_t> sync_ev;
-  // profiling
-  bool prof = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
-  // graph replay: a capture stream and a small cache of instantiated launch
-  // sequences, each with two pinned staging buffers used alternately
-  hipStream_t cap = nullptr;
-  struct GraphSlot {
-    hipGraphExec_t exec = nullptr;
-    void* staging = nullptr;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-  };
-  struct GraphEntry {
-    uint64_t key = 0;
-    uint64_t stamp = 0;
-    size_t head_bytes = 0;
-    GraphSlot slot[2];
-    int next = 0;
-  };
-  std::vector<GraphEntry> graphs;
-  uint64_t stamp = 0;
-  // autotuner results: problem-set signature -> tile size
-  std::vector<std::pair<uint64_t, int>> tuned;
-  // mixed precision: shifts re-solved in FP64 by the last call, and a pinned
-  // buffer for the gather/scatter lists (read by the copy kernel in place)
-  size_t last_fallback = 0;
-  void* lists = nullptr;
-  size_t lists_bytes = 0;
-  hipEvent_t lists_ev = nullptr;
-  bool lists_pending = false;
-};
+namespace hsrq {
 
-namespace {
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-struct Layout {
-  int ncols = 0;
-  std::vector<int32_t> coltype, colshift, colsrc, colconj;
-  std::vector<double> lr, li;
-};
-
-// Complex shifts first as aligned [re im] pairs, then real shifts, each group
-// in the caller's order (the real/complex split of Algorithm 15).
 Layout make_layout(int m, const double* wr, const double* wi) {
   Layout L;
   std::vector<int> ccol(m);
@@ -121,80 +57,12 @@ Layout make_layout(int m, const double* wr, const double* wi) {
   return L;
 }
 
-constexpr int kCrit = 16;   // columns of a critical task
-constexpr int kChunk = 128;  // rows per chunk of the final scan
-
-constexpr int kNbCandidates[2] = {64, 128};
-
-// FNV-1a over 64-bit words
-struct Sig {
-  uint64_t v = 1469598103934665603ull;
-  void add(uint64_t x) {
-    for (int b = 0; b < 8; ++b) {
-      v ^= (x >> (8 * b)) & 0xff;
-      v *= 1099511628211ull;
-    }
-  }
-};
-
 int count_cols(int m, const double* wi) {
   int c = 0;
   for (int l = 0; l < m; ++l) c += (wi[l] != 0.0) ? 2 : 1;
   return c;
 }
 
-// the autotuner's key: orders and column counts of the problem set
-uint64_t problem_signature(int count, const hsrq_problem_t* probs) {
-  Sig g;
-  g.add((uint64_t)count);
-  for (int p = 0; p < count; ++p) {
-    g.add((uint64_t)probs[p].n);
-    g.add((uint64_t)(probs[p].m > 0 ? count_cols(probs[p].m, probs[p].wi) : 0));
-  }
-  return g.v;
-}
-
-int heuristic_nb(int count, const hsrq_problem_t* probs) {
-  int nmax = 0;
-  for (int p = 0; p < count; ++p) nmax = std::max(nmax, probs[p].n);
-  return nmax >= 2048 ? 128 : 64;
-}
-
-// tile size: explicit option, else the autotuner's choice for this problem
-// set, else a size rule
-int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
-  if (o && (o->nb == 64 || o->nb == 128)) return o->nb;
-  if (h && !h->tuned.empty()) {
-    const uint64_t key = problem_signature(count, probs);
-    for (auto& e : h->tuned)
-      if (e.first == key) return e.second;
-  }
-  return heuristic_nb(count, probs);
-}
-
-struct ProbPlan {
-  int n, N, nb, ncols, ld, nblk;
-  Layout lay;
-  // byte offsets inside the workspace
-  size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
-  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
-  size_t o_zero, o_RSUM, o_HF, o_FLAG, o_RNUM, o_HN;
-};
-
-struct Plan {
-  int nb = 64;
-  int prec = 0;  // 1: FP32 tile-update products
-  std::vector<ProbPlan> pp;
-  std::vector<Task> tasks;
-  std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
-  std::vector<int2> blk_cols;
-  std::vector<int4> blk_prep, blk_init, blk_out, blk_fin;
-  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin;
-  size_t head_bytes, total_bytes;
-  size_t o_zero_all = 0, zero_count = 0;  // doubles
-};
-
-// Carve the workspace and build every host-side table.
 void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) {
   P.nb = nb_choice;
   const int nb = P.nb;
@@ -225,9 +93,9 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
       const int ncrit = (q.ncols + kCrit - 1) / kCrit;
       for (int L = 0; L < ncrit; ++L) {
         if (t == 0)
-          P.tasks.push_back(Task{p, TK_CHAIN, q.N - 1, L});
+          P.tasks.push_back(Task{p, task_code(TK_CHAIN, 0), q.N - 1, L});
         else
-          P.tasks.push_back(Task{p, TK_CRIT, q.N - t - 1, L});
+          P.tasks.push_back(Task{p, task_code(TK_CRIT, t), q.N - t - 1, L});
       }
     }
     P.ccnt[t] = (int)P.tasks.size() - P.coff[t];
@@ -238,7 +106,7 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
         if (q.ncols == 0 || q.N <= t) continue;
         const int jt = q.N - t;
         for (int i = 0; i < jt - 1; ++i)
-          for (int L = 0; L < q.nblk; ++L) P.tasks.push_back(Task{p, TK_FAR, i, L});
+          for (int L = 0; L < q.nblk; ++L) P.tasks.push_back(Task{p, task_code(TK_FAR, t), i, L});
       }
     }
     P.fcnt[t] = (int)P.tasks.size() - P.foff[t];
@@ -305,58 +173,6 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.o_FIN = off; off = align_up(off + sizeof(double) * (nch * 8 + 1) * q.ld);
   }
   P.total_bytes = off;
-}
-
-int ensure_staging(hsrq_handle_t h, size_t bytes) {
-  if (h->staging_pending) {
-    if (hipEventSynchronize(h->staging_ev) != hipSuccess) return HSRQ_ERR_HIP;
-    h->staging_pending = false;
-  }
-  if (h->staging_bytes >= bytes) return HSRQ_OK;
-  if (h->staging) hipHostFree(h->staging);
-  h->staging = nullptr;
-  h->staging_bytes = 0;
-  size_t want = std::max<size_t>(bytes, 1 << 20);
-  if (hipHostMalloc(&h->staging, want, hipHostMallocDefault) != hipSuccess) {
-    h->staging = nullptr;
-    return HSRQ_ERR_ALLOC;
-  }
-  h->staging_bytes = want;
-  return HSRQ_OK;
-}
-
-// Bracket one launch with profiling events when enabled.
-struct ProfScope {
-  hsrq_handle_t h;
-  int kind;
-  hipStream_t st;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(hsrq_handle_t h_, int k, hipStream_t s_ = nullptr) : h(h_), kind(k), st(s_ ? s_ : h_->stream) {
-    if (!h->prof) return;
-    a = get();
-    b = get();
-    if (a) hipEventRecord(a, st);
-  }
-  ~ProfScope() {
-    if (!h->prof || !a || !b) return;
-    hipEventRecord(b, st);
-    h->ev_used.push_back({kind, {a, b}});
-  }
-  hipEvent_t get() {
-    if (!h->ev_pool.empty()) {
-      hipEvent_t e = h->ev_pool.back();
-      h->ev_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-};
-
-template <class T>
-T* at(void* base, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
 // Writes the plan's head region (descriptors, task and block tables, column
@@ -427,6 +243,158 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
   if (!P.blk_out.empty()) std::memcpy(hb + P.o_bout, P.blk_out.data(), sizeof(int4) * P.blk_out.size());
 }
 
+int check_problem(const hsrq_problem_t& p) {
+  if (p.n < 1) return -2;
+  if (!p.H) return -3;
+  if (p.ldh < p.n) return -4;
+  if (p.m < 0) return -5;
+  if (p.m > 0 && !p.wr) return -6;
+  if (p.m > 0 && !p.wi) return -7;
+  if (p.m > 0 && !p.X) return -8;
+  if (p.ldx < p.n) return -9;
+  if (p.m > 0 && !p.scale_exp) return -10;
+  if (p.m > 0 && !p.scale_mant) return -11;
+  if (p.m > 0 && !p.info) return -12;
+  return 0;
+}
+
+}  // namespace hsrq
+
+
+struct hsrq_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  hipEvent_t staging_ev = nullptr;
+  bool staging_pending = false;
+  // second stream for the far-tile kernels, and fork/join events
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> sync_ev;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  // graph replay: a capture stream and a small cache of instantiated launch
+  // sequences, each with two pinned staging buffers used alternately
+  hipStream_t cap = nullptr;
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    void* staging = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  struct GraphEntry {
+    uint64_t key = 0;
+    uint64_t stamp = 0;
+    size_t head_bytes = 0;
+    GraphSlot slot[2];
+    int next = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t stamp = 0;
+  // autotuner results: problem-set signature -> tile size
+  std::vector<std::pair<uint64_t, int>> tuned;
+  // mixed precision: shifts re-solved in FP64 by the last call, and a pinned
+  // buffer for the gather/scatter lists (read by the copy kernel in place)
+  size_t last_fallback = 0;
+  void* lists = nullptr;
+  size_t lists_bytes = 0;
+  hipEvent_t lists_ev = nullptr;
+  bool lists_pending = false;
+};
+
+namespace {
+
+constexpr int kNbCandidates[2] = {64, 128};
+
+// FNV-1a over 64-bit words
+struct Sig {
+  uint64_t v = 1469598103934665603ull;
+  void add(uint64_t x) {
+    for (int b = 0; b < 8; ++b) {
+      v ^= (x >> (8 * b)) & 0xff;
+      v *= 1099511628211ull;
+    }
+  }
+};
+
+// the autotuner's key: orders and column counts of the problem set
+uint64_t problem_signature(int count, const hsrq_problem_t* probs) {
+  Sig g;
+  g.add((uint64_t)count);
+  for (int p = 0; p < count; ++p) {
+    g.add((uint64_t)probs[p].n);
+    g.add((uint64_t)(probs[p].m > 0 ? count_cols(probs[p].m, probs[p].wi) : 0));
+  }
+  return g.v;
+}
+
+int heuristic_nb(int count, const hsrq_problem_t* probs) {
+  int nmax = 0;
+  for (int p = 0; p < count; ++p) nmax = std::max(nmax, probs[p].n);
+  return nmax >= 2048 ? 128 : 64;
+}
+
+// tile size: explicit option, else the autotuner's choice for this problem
+// set, else a size rule
+int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
+  if (o && (o->nb == 64 || o->nb == 128)) return o->nb;
+  if (h && !h->tuned.empty()) {
+    const uint64_t key = problem_signature(count, probs);
+    for (auto& e : h->tuned)
+      if (e.first == key) return e.second;
+  }
+  return heuristic_nb(count, probs);
+}
+
+int ensure_staging(hsrq_handle_t h, size_t bytes) {
+  if (h->staging_pending) {
+    if (hipEventSynchronize(h->staging_ev) != hipSuccess) return HSRQ_ERR_HIP;
+    h->staging_pending = false;
+  }
+  if (h->staging_bytes >= bytes) return HSRQ_OK;
+  if (h->staging) hipHostFree(h->staging);
+  h->staging = nullptr;
+  h->staging_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 20);
+  if (hipHostMalloc(&h->staging, want, hipHostMallocDefault) != hipSuccess) {
+    h->staging = nullptr;
+    return HSRQ_ERR_ALLOC;
+  }
+  h->staging_bytes = want;
+  return HSRQ_OK;
+}
+
+// Bracket one launch with profiling events when enabled.
+struct ProfScope {
+  hsrq_handle_t h;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hsrq_handle_t h_, int k, hipStream_t s_ = nullptr) : h(h_), kind(k), st(s_ ? s_ : h_->stream) {
+    if (!h->prof) return;
+    a = get();
+    b = get();
+    if (a) hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!h->prof || !a || !b) return;
+    hipEventRecord(b, st);
+    h->ev_used.push_back({kind, {a, b}});
+  }
+  hipEvent_t get() {
+    if (!h->ev_pool.empty()) {
+      hipEvent_t e = h->ev_pool.back();
+      h->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
 int ensure_sync_events(hsrq_handle_t h, int T) {
   if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
   while ((int)h->sync_ev.size() < 2 * T + 2) {
@@ -472,11 +440,11 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s);
-      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], t, s);
+      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], s);
     }
     if (P.fcnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_FAR, a);
-      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], t, a);
+      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], a);
     }
     hipEventRecord(ev[2 * t], s);
     hipEventRecord(ev[2 * t + 1], a);
@@ -860,21 +828,6 @@ size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const
   }
   (void)h;
   return b;
-}
-
-int check_problem(const hsrq_problem_t& p) {
-  if (p.n < 1) return -2;
-  if (!p.H) return -3;
-  if (p.ldh < p.n) return -4;
-  if (p.m < 0) return -5;
-  if (p.m > 0 && !p.wr) return -6;
-  if (p.m > 0 && !p.wi) return -7;
-  if (p.m > 0 && !p.X) return -8;
-  if (p.ldx < p.n) return -9;
-  if (p.m > 0 && !p.scale_exp) return -10;
-  if (p.m > 0 && !p.scale_mant) return -11;
-  if (p.m > 0 && !p.info) return -12;
-  return 0;
 }
 
 }  // namespace

@@ -1,0 +1,79 @@
+// hsrq_plan.h -- host-side planning shared by the solve entry points and
+// the serving loop: column layout, tiling, per-step task lists, workspace
+// carving, and the kernel launch wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "hsrq.h"
+#include "hsrq_common.h"
+
+namespace hsrq {
+
+void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
+void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
+void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st);
+void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st);
+void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
+void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
+void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
+void launch_fill(double* p, long long cnt, double v, hipStream_t st);
+void launch_copy(const CopyEnt* ents, int count, hipStream_t st);
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  int ncols = 0;
+  std::vector<int32_t> coltype, colshift, colsrc, colconj;
+  std::vector<double> lr, li;
+};
+
+constexpr int kCrit = 16;   // columns of a critical task
+constexpr int kChunk = 128;  // rows per chunk of the final scan
+
+struct ProbPlan {
+  int n, N, nb, ncols, ld, nblk;
+  Layout lay;
+  // byte offsets inside the workspace
+  size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
+  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
+  size_t o_zero, o_RSUM, o_HF, o_FLAG, o_RNUM, o_HN;
+};
+
+struct Plan {
+  int nb = 64;
+  int prec = 0;  // 1: FP32 tile-update products
+  std::vector<ProbPlan> pp;
+  std::vector<Task> tasks;
+  std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
+  std::vector<int2> blk_cols;
+  std::vector<int4> blk_prep, blk_init, blk_out, blk_fin;
+  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin;
+  size_t head_bytes, total_bytes;
+  size_t o_zero_all = 0, zero_count = 0;  // doubles
+};
+
+// Carve the workspace and build every host-side table.
+// Complex shifts first as aligned [re im] pairs, then real shifts, each group
+// in the caller's order (the real/complex split of Algorithm 15).
+Layout make_layout(int m, const double* wr, const double* wi);
+int count_cols(int m, const double* wi);
+// Carve the workspace and build every host-side table for tile size nb.
+void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb);
+// Writes the plan's head region (descriptors, task and block tables, column
+// metadata) into the host image hb.
+void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* work, const hsrq_opts_t* o,
+                  char* hb);
+// 0, or -k for an invalid k-th argument of the single-problem call
+int check_problem(const hsrq_problem_t& p);
+
+template <class T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace hsrq

@@ -1,0 +1,138 @@
+"""GPU: the serving loop (continuous batching under an HBM budget) through
+the C ABI: each result is the same alone and in the mix, and matches the
+reference."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.parity import compare
+from workloads import generators as g
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(A):
+    A = np.asarray(A, dtype=np.float64)
+    return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+
+
+def host(T):
+    return T.t().contiguous().cpu().numpy().T.copy()
+
+
+def requests(seed, count, nmax):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        n = int(np.exp(rng.uniform(np.log(40), np.log(nmax))))
+        H = g.random_hessenberg(n, rng)
+        ev = np.linalg.eigvals(H)
+        tol = 1e-12 * max(1.0, np.abs(ev).max())
+        real = ev[np.abs(ev.imag) <= tol].real
+        cplx = ev[ev.imag > tol]
+        k = int(rng.integers(1, max(2, n // 8)))
+        nc = min(int(round(0.3 * k)), cplx.size)
+        nr = min(k - nc, real.size)
+        wr = list(rng.choice(real, nr, replace=False)) + list(cplx[:nc].real)
+        wi = [0.0] * nr + list(cplx[:nc].imag)
+        if not wr:
+            wr, wi = [0.3], [0.0]
+        wr, wi = np.array(wr), np.array(wi)
+        out.append((H, wr, wi, rng.standard_normal((n, g.ncols(wi)))))
+    return out
+
+
+def drain(srv, tags, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tags):
+        for c in srv.poll(wait_ms=20):
+            got[c["tag"]] = c
+        assert time.time() - t0 < timeout, "server did not finish"
+    return got
+
+
+def run_alone(Server, reqs, **kw):
+    srv = Server(0, **kw)
+    outs = []
+    for k, (H, wr, wi, B) in enumerate(reqs):
+        print(f"[gpu] serving alone: request {k} n={H.shape[0]} m={len(wr)}", flush=True)
+        X = dev(B)
+        o = srv.submit(dev(H), wr, wi, X, k)
+        c = drain(srv, [k])[k]
+        assert c["status"] == 0
+        torch.cuda.synchronize()
+        outs.append((host(X), o[0].cpu().numpy(), o[1].cpu().numpy(), o[2].cpu().numpy()))
+    srv.close()
+    return outs
+
+
+def run_mix(Server, reqs, budget=200 * 10 ** 9, **kw):
+    srv = Server(0, budget_bytes=budget, **kw)
+    Xs, outs, Hd = [], [], [dev(H) for H, *_ in reqs]
+    rng = np.random.default_rng(3)
+    for k, (H, wr, wi, B) in enumerate(reqs):
+        X = dev(B)
+        Xs.append(X)
+        outs.append(srv.submit(Hd[k], wr, wi, X, k))
+        time.sleep(float(rng.uniform(0, 0.002)))  # staggered arrivals, some while others run
+    print(f"[gpu] serving mix: {len(reqs)} requests submitted", flush=True)
+    done = drain(srv, list(range(len(reqs))))
+    assert all(c["status"] == 0 for c in done.values())
+    torch.cuda.synchronize()
+    res = [(host(X), o[0].cpu().numpy(), o[1].cpu().numpy(), o[2].cpu().numpy()) for X, o in zip(Xs, outs)]
+    srv.close()
+    return res, done
+
+
+def test_alone_equals_mix_and_reference():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Server
+    reqs = requests(31, 14, 900)
+    alone = run_alone(Server, reqs, nb=64)
+    mix, done = run_mix(Server, reqs, nb=64)
+    overlap = sum(1 for a in done.values() for b in done.values()
+                  if a is not b and a["t_start"] < b["t_done"] and b["t_start"] < a["t_done"])
+    print("overlapping request pairs:", overlap // 2)
+    for (H, wr, wi, B), A, M in zip(reqs, alone, mix):
+        for x, y in zip(A, M):  # same kernels, same inputs: bit for bit
+            assert np.array_equal(x, y)
+        Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
+        compare(M[0], M[1], M[2], M[3], Yo, Eo, muo, infoo, wi, dir_tol=1e-9, mu_tol=100 * H.shape[0] * 2.0 ** -52)
+
+
+def test_tight_budget_and_oversized_request():
+    """A budget that holds only a few requests at a time still completes every
+    request with the same results; a request that can never fit is refused."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Server
+    reqs = requests(32, 10, 500)
+    free_mix, _ = run_mix(Server, reqs, nb=64)
+    tight, done = run_mix(Server, reqs, budget=40 * 10 ** 6, nb=64)
+    for A, B in zip(free_mix, tight):
+        for x, y in zip(A, B):
+            assert np.array_equal(x, y)
+    srv = Server(0, budget_bytes=4096, nb=64)
+    H, wr, wi, B = reqs[0]
+    assert srv.submit(dev(H), wr, wi, dev(B), 99) is None
+    srv.close()
+
+
+def test_mixed_precision_serving():
+    """Precision 1 in the serving loop: every result meets the FP64 bars
+    against the reference (the failing shifts re-solved in FP64)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Server
+    reqs = requests(33, 8, 700)
+    mix, done = run_mix(Server, reqs, nb=64, precision=1)
+    print("fallback per request:", [done[k]["fallback"] for k in sorted(done)])
+    for (H, wr, wi, B), M in zip(reqs, mix):
+        Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
+        compare(M[0], M[1], M[2], M[3], Yo, Eo, muo, infoo, wi, dir_tol=1e-8, mu_tol=1e-2, straddle_tol=1e-2)

@@ -369,3 +369,31 @@ def c5_request(pool_entry, rng, complex_frac=0.3):
     npair = min(k - nreal, avail_c)
     wr, wi, _ = pick_shifts(ev, nreal, npair, rng=rng)
     return dict(H=H, wr=wr, wi=wi, B=ones_start(n, wi))
+
+
+def c5_requests(pool, count, seed=1005, complex_frac=0.3):
+    """``count`` serving requests drawn like ``c5_request`` (a uniformly chosen
+    pool matrix, U{1..n/8} shifts, 30% complex pairs, chosen at random among
+    its host eigenvalues), without the separations or starting vectors (the
+    starts are all ones).  Returns a list of (pool index, wr, wi)."""
+    rng = np.random.default_rng(seed)
+    split = []
+    for e in pool:
+        ev = np.asarray(e["ev"])
+        tol = 1e-12 * max(1.0, np.abs(ev).max())
+        split.append((ev[np.abs(ev.imag) <= tol].real, ev[ev.imag > tol]))
+    out = []
+    for _ in range(count):
+        b = int(rng.integers(len(pool)))
+        n = pool[b]["H"].shape[0]
+        real, cplx = split[b]
+        k = int(rng.integers(1, max(1, n // 8) + 1))
+        npair = int(round(complex_frac * k))
+        nreal = min(k - npair, real.size)
+        npair = min(k - nreal, cplx.size)
+        ir = rng.permutation(real.size)[:nreal]
+        ic = rng.permutation(cplx.size)[:npair]
+        wr = np.concatenate([real[ir], cplx[ic].real])
+        wi = np.concatenate([np.zeros(ir.size), cplx[ic].imag])
+        out.append((b, wr, wi))
+    return out
