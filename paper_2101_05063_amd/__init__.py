@@ -166,7 +166,7 @@ class Solver:
                                             ctypes.byref(o), ctypes.byref(out)), "hsrq_workspace_size")
         return out.value
 
-    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, stream=None):
+    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None):
         """Solve in place: X (device, n x ncols) holds the starting vectors and
         receives the unit vectors.  Returns (scale_exp, scale_mant, info,
         resid) device tensors of length m."""
@@ -185,7 +185,7 @@ class Solver:
         mu = torch.empty(m, dtype=torch.float64, device=dev)
         info = torch.empty(m, dtype=torch.int32, device=dev)
         res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
-        o = _opts(nb, precision, residual)
+        o = _opts(nb, precision, residual, graph)
         need = self.workspace_size(n, wi, nb, precision)
         wp, wb = self.workspace(need)
         self._stream(stream)

@@ -32,7 +32,7 @@ struct Layout {
   std::vector<double> lr, li;
 };
 
-constexpr int kCrit = 16;   // columns of a critical task
+constexpr int kCrit = 8;    // columns of a critical task
 constexpr int kChunk = 128;  // rows per chunk of the final scan
 
 struct ProbPlan {
