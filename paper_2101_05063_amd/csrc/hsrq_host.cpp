@@ -443,6 +443,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
       launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], s);
     }
     if (P.fcnt[t] > 0) {
+      if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
       ProfScope ps(h, HSRQ_K_FAR, a);
       launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], a);
     }

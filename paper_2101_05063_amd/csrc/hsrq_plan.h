@@ -22,6 +22,7 @@ void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st)
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
 void launch_fill(double* p, long long cnt, double v, hipStream_t st);
 void launch_copy(const CopyEnt* ents, int count, hipStream_t st);
+void launch_gate(hipStream_t st);
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
