@@ -367,20 +367,24 @@ int ensure_staging(hsrq_handle_t h, size_t bytes) {
 }
 
 // Bracket one launch with profiling events when enabled.
+// attach = true: the events go with a single kernel dispatch (start and end
+// of that kernel, see launch_crit) instead of being recorded around it
 struct ProfScope {
   hsrq_handle_t h;
   int kind;
   hipStream_t st;
+  bool attach;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(hsrq_handle_t h_, int k, hipStream_t s_ = nullptr) : h(h_), kind(k), st(s_ ? s_ : h_->stream) {
+  ProfScope(hsrq_handle_t h_, int k, hipStream_t s_ = nullptr, bool attach_ = false)
+      : h(h_), kind(k), st(s_ ? s_ : h_->stream), attach(attach_) {
     if (!h->prof) return;
     a = get();
     b = get();
-    if (a) hipEventRecord(a, st);
+    if (a && !attach) hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!h->prof || !a || !b) return;
-    hipEventRecord(b, st);
+    if (!attach) hipEventRecord(b, st);
     h->ev_used.push_back({kind, {a, b}});
   }
   hipEvent_t get() {
@@ -439,13 +443,13 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
       hipStreamWaitEvent(a, ev[2 * (t - 1)], 0);
     }
     if (P.ccnt[t] > 0) {
-      ProfScope ps(h, HSRQ_K_CRIT, s);
-      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], s);
+      ProfScope ps(h, HSRQ_K_CRIT, s, true);
+      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
     }
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
-      ProfScope ps(h, HSRQ_K_FAR, a);
-      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], a);
+      ProfScope ps(h, HSRQ_K_FAR, a, true);
+      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
     }
     hipEventRecord(ev[2 * t], s);
     hipEventRecord(ev[2 * t + 1], a);

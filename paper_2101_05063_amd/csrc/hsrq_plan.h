@@ -15,8 +15,10 @@ namespace hsrq {
 
 void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st);
-void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st);
+void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
+                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
