@@ -179,102 +179,6 @@ def cpu_baseline(c, seconds, cores):
                        f"{dt:.1f} s wall on {cores} threads")
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
-
-
-def load_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter runs, valid
-    only for the kernel sources they were taken on."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    d = json.load(open(TRAFFIC_FILE))
-    if d.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
-
-
-def _pmc_rows(path):
-    """(kernel name, counter value) rows of a rocprofv3 counter_collection.csv."""
-    import csv
-    out = []
-    with open(path, newline="") as f:
-        for r in csv.DictReader(f):
-            out.append((r["Kernel_Name"], float(r["Counter_Value"])))
-    return out
-
-
-def ingest_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
-    """Writes profiles/traffic_c3.json from two counter runs of the benchmark
-    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) and the same two counters
-    read on the plain copy of --copy-probe, whose true traffic is copy_bytes
-    read and copy_bytes written per dispatch."""
-    import statistics
-
-    def per_kernel(rows):
-        acc = {}
-        for name, v in rows:
-            key = name.split("(")[0].replace("void ", "").strip()
-            acc.setdefault(key, []).append(v)
-        return acc
-
-    def copy_value(rows):
-        vals = [v for name, v in rows if "copy" in name.lower()]
-        return statistics.median(vals)
-
-    f_copy = copy_value(_pmc_rows(copy_fetch_csv)) * 1024.0
-    w_copy = copy_value(_pmc_rows(copy_write_csv)) * 1024.0
-    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
-    fk, wk = per_kernel(_pmc_rows(fetch_csv)), per_kernel(_pmc_rows(write_csv))
-    kernels = {}
-    for k in fk:
-        if k in wk:
-            fb = statistics.mean(fk[k]) * 1024.0 * f_scale
-            wb = statistics.mean(wk[k]) * 1024.0 * w_scale
-            kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-                          "bytes_per_launch": fb + wb, "launches": len(fk[k])}
-    d = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
-         "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
-    with open(TRAFFIC_FILE, "w") as f:
-        json.dump(d, f, indent=1, sort_keys=True)
-    print(json.dumps(d, indent=1, sort_keys=True))
-
-
-COPY_BYTES = 256 << 20
-
-
-def copy_probe():
-    """A plain device copy of known size for calibrating the HBM counters."""
-    import torch
-    n = COPY_BYTES // 8
-    a = torch.rand(n, dtype=torch.float64, device="cuda:0")
-    b = torch.empty_like(a)
-    for _ in range(5):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
-
-
-def cpu_baseline(c, seconds, cores):
-    """The plain C reference on a bounded sample of the same shifts."""
-    import numpy as np
-    from oracle import oracle as O
-    H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
-    O.build()
-    k = max(1, cores)
-    t0 = time.perf_counter()
-    O.batch(H, wr[:k], wi[:k], B[:, :k], nthreads=cores)
-    t1 = time.perf_counter() - t0
-    per_round = t1
-    rounds = max(1, int(seconds / max(per_round, 1e-3)))
-    s = min(len(wr), k * rounds)
-    t0 = time.perf_counter()
-    O.batch(H, wr[:s], wi[:s], B[:, :s], nthreads=cores)
-    dt = time.perf_counter() - t0
-    return dict(value=s / dt, unit="eigenvectors/s", cores=cores, kind="oracle",
-                sample=f"first {s} of the {len(wr)} shifts (n={H.shape[0]}), {dt:.1f} s wall on {cores} threads")
-
-
 def error_vs_reference(probs_h, probs_d, outs, cores):
     """Per-result error of a GPU solve against the plain CPU reference (every
     shift of every problem): 1 - |cos| of the directions, exponent mismatches
@@ -578,7 +482,7 @@ def main():
     for kind, fam in (("crit", "k_crit"), ("far", "k_far")):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
-        name = f"hsrq::{fam}<{nbv}>"
+        name = f"hsrq::{fam}<{nbv}, {'true' if args.precision == 1 else 'false'}>"
         ach = fl[kind] / (per_solve * 1e-3) / 1e12 if per_solve > 0 else 0.0
         kern[kind] = {"kernel": name, "ms_per_step": round(per_solve, 4),
                       "launches_per_step": launches / args.steps,
