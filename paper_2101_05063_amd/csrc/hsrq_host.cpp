@@ -63,6 +63,22 @@ int count_cols(int m, const double* wi) {
   return c;
 }
 
+// Workgroups of a launch go to the 8 XCDs of the device in turn (workgroup b
+// to XCD b % 8), and each XCD has its own L2.  Reorder a task list so that
+// XCD x receives a contiguous run of it: the column blocks of one tile row,
+// which share the H tile, then land on one XCD (two at a run boundary).
+constexpr int kXcds = 8;
+void xcd_order(Task* t, int n) {
+  if (n <= kXcds) return;
+  std::vector<Task> src(t, t + n);
+  int start = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    const int cnt = (n - x + kXcds - 1) / kXcds;  // workgroups b < n with b % 8 == x
+    for (int j = 0; j < cnt; ++j) t[x + kXcds * j] = src[start + j];
+    start += cnt;
+  }
+}
+
 void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) {
   P.nb = nb_choice;
   const int nb = P.nb;
@@ -110,6 +126,7 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
       }
     }
     P.fcnt[t] = (int)P.tasks.size() - P.foff[t];
+    xcd_order(P.tasks.data() + P.foff[t], P.fcnt[t]);
   }
   for (int p = 0; p < count; ++p) {
     const ProbPlan& q = P.pp[p];
