@@ -36,7 +36,6 @@ struct Layout {
 };
 
 constexpr int kCrit = 8;    // columns of a critical task
-constexpr int kChunk = 128;  // rows per chunk of the final scan
 
 struct ProbPlan {
   int n, N, nb, ncols, ld, nblk;
