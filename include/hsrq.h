@@ -70,6 +70,10 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 64 or 128; 0 = the choice of hsrq_autotune for this problem
  *                 set if it ran on the handle, else 128 when the largest
  *                 order is >= 2048 and 64 otherwise.
+ *   Any other value of nb, precision (0, 1), residual (0, 1) or graph
+ *   (-1, 0, 1) makes the call fail with the position of opts (LAPACK style:
+ *   -16 for hsrq_dhsrq3, -5 for hsrq_workspace_size) or HSRQ_ERR_ARG for the
+ *   batched, tuning and debug calls; nothing is substituted silently.
  *   cols_per_block reserved (shift blocks are fixed by the kernels: 64
  *                 columns per far-tile block, 16 per critical block).
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the

@@ -353,6 +353,17 @@ int heuristic_nb(int count, const hsrq_problem_t* probs) {
   return nmax >= 2048 ? 128 : 64;
 }
 
+// options outside their documented values are rejected, never replaced by a
+// default (the kernels exist for tile sizes 64 and 128 only)
+bool opts_ok(const hsrq_opts_t* o) {
+  if (!o) return true;
+  if (o->nb != 0 && o->nb != 64 && o->nb != 128) return false;
+  if (o->precision != 0 && o->precision != 1) return false;
+  if (o->residual != 0 && o->residual != 1) return false;
+  if (o->graph < -1 || o->graph > 1) return false;
+  return true;
+}
+
 // tile size: explicit option, else the autotuner's choice for this problem
 // set, else a size rule
 int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
@@ -420,7 +431,10 @@ int ensure_sync_events(hsrq_handle_t h, int T) {
   if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
   while ((int)h->sync_ev.size() < 2 * T + 2) {
     hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return HSRQ_ERR_HIP;
+    // ordering between the handle's two streams on one device: a release at
+    // device scope is enough, and it spares the system-scope cache writeback
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
+      return HSRQ_ERR_HIP;
     h->sync_ev.push_back(e);
   }
   return HSRQ_OK;
@@ -940,7 +954,7 @@ int hsrq_set_stream(hsrq_handle_t h, void* stream) {
 
 int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
                                 const hsrq_opts_t* opts, size_t* bytes) {
-  if (!h || count < 0 || (count > 0 && !problems) || !bytes) return HSRQ_ERR_ARG;
+  if (!h || count < 0 || (count > 0 && !problems) || !bytes || !opts_ok(opts)) return HSRQ_ERR_ARG;
   for (int p = 0; p < count; ++p)
     if (problems[p].n < 1 || problems[p].m < 0 || (problems[p].m > 0 && !problems[p].wi)) return HSRQ_ERR_ARG;
   *bytes = plan_bytes(h, count, problems, opts);
@@ -953,6 +967,7 @@ int hsrq_workspace_size(hsrq_handle_t h, int n, int m, const double* wi, const h
   if (n < 1) return -2;
   if (m < 0) return -3;
   if (m > 0 && !wi) return -4;
+  if (!opts_ok(opts)) return -5;
   if (!bytes) return -6;
   std::vector<double> wr(m > 0 ? m : 1, 0.0);
   hsrq_problem_t p{};
@@ -969,13 +984,14 @@ int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh, int m, const d
   int st = check_problem(p);
   if (st) return st;
   if (!work) return -14;
+  if (!opts_ok(opts)) return -16;
   if (m == 0) return HSRQ_OK;
   return run(h, 1, &p, work, work_bytes, opts, false);
 }
 
 int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work,
                         size_t work_bytes, const hsrq_opts_t* opts) {
-  if (!h || count < 0 || (count > 0 && !problems)) return HSRQ_ERR_ARG;
+  if (!h || count < 0 || (count > 0 && !problems) || !opts_ok(opts)) return HSRQ_ERR_ARG;
   for (int p = 0; p < count; ++p)
     if (check_problem(problems[p])) return HSRQ_ERR_ARG;
   if (count == 0) return HSRQ_OK;
@@ -984,7 +1000,7 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
 
 int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work, size_t work_bytes,
                   const hsrq_opts_t* opts, int* best_nb, double* ms) {
-  if (!h || count < 1 || !problems || !best_nb || !work) return HSRQ_ERR_ARG;
+  if (!h || count < 1 || !problems || !best_nb || !work || !opts_ok(opts)) return HSRQ_ERR_ARG;
   for (int p = 0; p < count; ++p)
     if (check_problem(problems[p])) return HSRQ_ERR_ARG;
   hsrq_opts_t o{};
@@ -1044,7 +1060,7 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
 int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts, void* work,
                     const double** C, const double** S, const double** PHI, const double** V, int* ld,
                     int* nb, int32_t* col_of) {
-  if (!h || n < 1 || m < 0 || (m > 0 && !wi) || !work) return HSRQ_ERR_ARG;
+  if (!h || n < 1 || m < 0 || (m > 0 && !wi) || !work || !opts_ok(opts)) return HSRQ_ERR_ARG;
   std::vector<double> wr(m > 0 ? m : 1, 0.0);
   hsrq_problem_t p{};
   p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;

@@ -238,6 +238,29 @@ def test_invalid_inputs(solver):
     H = g.random_hessenberg(n, 3)
     Yg, Eg, mug, infog = run_gpu(solver, H, np.array([np.nan, 0.3]), np.array([0.0, 0.0]), np.ones((n, 2)))
     assert infog[0] == 3 and infog[1] in (0, 1)
+    # options outside their documented values are rejected, not replaced:
+    # the workspace query reports the position of its opts (-5), the solve
+    # that of its own (-16; the binding's query does not pass graph) ...
+    B1 = np.ones((n, 1))
+    for kw, st in ((dict(nb=256), -5), (dict(nb=32), -5), (dict(precision=2), -5), (dict(graph=3), -16)):
+        with pytest.raises(RuntimeError, match=f"status {st}$"):
+            solver.solve(dev(H), wr[:1], wi[:1], dev(B1), **kw)
+    # ... and so does the solve itself (-16), before anything is launched
+    import ctypes
+    from paper_2101_05063_amd import _opts
+    Hd, Xd = dev(H), dev(B1)
+    E = torch.zeros(1, dtype=torch.int32, device=Hd.device)
+    mu = torch.zeros(1, dtype=torch.float64, device=Hd.device)
+    inf = torch.zeros(1, dtype=torch.int32, device=Hd.device)
+    wp, wb = solver.workspace(solver.workspace_size(n, wi[:1]))
+    w1, i1 = np.ascontiguousarray(wr[:1]), np.ascontiguousarray(wi[:1])
+    bad = _opts(nb=256)
+    st = solver.lib.hsrq_dhsrq3(solver.h, n, Hd.data_ptr(), n, 1, w1.ctypes.data_as(ctypes.c_void_p),
+                                i1.ctypes.data_as(ctypes.c_void_p), Xd.data_ptr(), n, E.data_ptr(),
+                                mu.data_ptr(), inf.data_ptr(), None, ctypes.c_void_p(wp), wb, ctypes.byref(bad))
+    assert st == -16
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Xd), B1)
 
 
 def test_bad_system_full_size(solver):
