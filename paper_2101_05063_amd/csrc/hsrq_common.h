@@ -21,7 +21,7 @@ constexpr int kTExp = 1000;        // stored magnitudes stay below 2^kTExp
 constexpr int kNegExp = -100000;   // exponent of zero
 constexpr int kSingExp = 1 << 29;  // segment exponent of an exactly singular R(1,1)
 constexpr int kCB = 64;            // columns per block (shifts-per-block b_c, in columns)
-constexpr int kChunk = 128;           // rows per chunk of the final scan (host tables and kernels)
+constexpr int kChunk = 32;         // rows per chunk of the final scan (host tables and kernels)
 
 enum ColType : int32_t { CT_REAL = 0, CT_CRE = 1, CT_CIM = 2 };
 enum TaskType : int32_t { TK_CHAIN = 0, TK_CRIT = 1, TK_FAR = 2 };
