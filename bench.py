@@ -395,6 +395,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--rotations", type=int, default=1, choices=[0, 1],
+                    help="0: off-diagonal rotations one at a time (bit-identical to the paper's order); "
+                         "1: folded into one matrix per tile column and applied on the matrix cores")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
@@ -451,7 +454,8 @@ def main():
             A.copy_(Bd)
         torch.cuda.synchronize()
         for k in range(args.warmup):
-            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph)
+            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph,
+                          rotations=args.rotations)
         torch.cuda.synchronize()
         if prof:
             solver.profile(True)
@@ -460,7 +464,8 @@ def main():
         t0 = time.perf_counter()
         outs = []
         for k in range(args.steps):
-            outs.append(solver.dhsrq3(Hd, wr, wi, Xs[k], nb=nb, precision=args.precision, graph=graph))
+            outs.append(solver.dhsrq3(Hd, wr, wi, Xs[k], nb=nb, precision=args.precision, graph=graph,
+                                      rotations=args.rotations))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pr = None
@@ -487,6 +492,8 @@ def main():
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
         name = f"hsrq::{fam}<{nbv}, {'true' if args.precision == 1 else 'false'}>"
+        if kind == "far" and args.precision == 0 and args.rotations == 1:
+            name = f"hsrq::k_far3<{nbv}>"
         ach = fl[kind] / (per_solve * 1e-3) / 1e12 if per_solve > 0 else 0.0
         kern[kind] = {"kernel": name, "ms_per_step": round(per_solve, 4),
                       "launches_per_step": launches / args.steps,
@@ -509,7 +516,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
         "config": {"workload": "graded random unreduced Hessenberg n=8000, 1000 real eigenvalue shifts, "
                                "all-ones starts (D_ii = 10^(300 i/n))",
-                   "n": n, "m": m, "nb": nbv, "precision": args.precision, "graph": graph == 1},
+                   "n": n, "m": m, "nb": nbv, "precision": args.precision, "rotations": args.rotations,
+                   "graph": graph == 1},
         "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
         "ms_per_step_with_kernel_events": round(ms_prof, 4),
         "roofline": roof,

@@ -70,8 +70,8 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 64 or 128; 0 = the choice of hsrq_autotune for this problem
  *                 set if it ran on the handle, else 128 when the largest
  *                 order is >= 2048 and 64 otherwise.
- *   Any other value of nb, precision (0, 1), residual (0, 1) or graph
- *   (-1, 0, 1) makes the call fail with the position of opts (LAPACK style:
+ *   Any other value of nb, precision (0, 1), residual (0, 1), graph
+ *   (-1, 0, 1) or rotations (0, 1) makes the call fail with the position of opts (LAPACK style:
  *   -16 for hsrq_dhsrq3, -5 for hsrq_workspace_size) or HSRQ_ERR_ARG for the
  *   batched, tuning and debug calls; nothing is substituted silently.
  *   cols_per_block reserved (shift blocks are fixed by the kernels: 64
@@ -87,6 +87,18 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 kernel by kernel; 0 = default (graph for batched calls,
  *                 kernel by kernel for single calls).  Profiling forces
  *                 kernel-by-kernel launches.
+ *   rotations     how the rotations of a tile column reach the cross-over
+ *                 columns of the tile rows above its superdiagonal tile
+ *                 (ReduceOffdiag, Sec. 3.1): 0 = one rotation at a time in
+ *                 the order of Alg. 1 (default), so that every rotation,
+ *                 R(k,k) and working column is bit-identical to that order;
+ *                 1 = the NB rotations of a tile column folded into one
+ *                 matrix W and applied as the product H(I, J-) W on the
+ *                 matrix cores.  Form 1 agrees with form 0 to rounding: the
+ *                 rotations, and the scale exponent of a shift whose system
+ *                 is nearly singular, can then differ as far as the
+ *                 conditioning allows.  The FP32 tile products of
+ *                 precision 1 always use form 0.
  */
 typedef struct {
     int nb;
@@ -94,7 +106,8 @@ typedef struct {
     int precision;
     int residual;
     int graph;
-    int reserved[3];
+    int rotations;
+    int reserved[2];
 } hsrq_opts_t;
 
 /* One problem of a batched call.  H, X, scale_exp, scale_mant, info and

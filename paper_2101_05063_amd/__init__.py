@@ -32,7 +32,8 @@ KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
 class HsrqOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("cols_per_block", ctypes.c_int), ("precision", ctypes.c_int),
-                ("residual", ctypes.c_int), ("graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("residual", ctypes.c_int), ("graph", ctypes.c_int), ("rotations", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class HsrqCompletion(ctypes.Structure):
@@ -95,12 +96,13 @@ def _check(st, what):
         raise RuntimeError(f"{what} failed with status {st}")
 
 
-def _opts(nb=0, precision=0, residual=False, graph=0):
+def _opts(nb=0, precision=0, residual=False, graph=0, rotations=0):
     o = HsrqOpts()
     o.nb = int(nb or 0)
     o.precision = int(precision)
     o.residual = 1 if residual else 0
     o.graph = int(graph)
+    o.rotations = int(rotations)
     return o
 
 
@@ -166,10 +168,12 @@ class Solver:
                                             ctypes.byref(o), ctypes.byref(out)), "hsrq_workspace_size")
         return out.value
 
-    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None):
+    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0):
         """Solve in place: X (device, n x ncols) holds the starting vectors and
         receives the unit vectors.  Returns (scale_exp, scale_mant, info,
-        resid) device tensors of length m."""
+        resid) device tensors of length m.  rotations=1 applies the
+        off-diagonal rotations of a tile column as one product on the matrix
+        cores (default 0: one at a time, bit-identical to Alg. 1's order)."""
         torch = self.torch
         n = H.shape[0]
         wr = np.ascontiguousarray(wr, dtype=np.float64)
@@ -185,7 +189,7 @@ class Solver:
         mu = torch.empty(m, dtype=torch.float64, device=dev)
         info = torch.empty(m, dtype=torch.int32, device=dev)
         res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
-        o = _opts(nb, precision, residual, graph)
+        o = _opts(nb, precision, residual, graph, rotations)
         need = self.workspace_size(n, wi, nb, precision)
         wp, wb = self.workspace(need)
         self._stream(stream)
@@ -229,14 +233,14 @@ class Solver:
             a.resid = res.data_ptr() if res is not None else None
         return arr, keep, outs
 
-    def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None):
+    def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0):
         """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
         solved in place).  Returns a list of (E, mu, info, resid).  graph: 1
         replay as a HIP graph, -1 launch kernel by kernel, 0 library default
         (graph)."""
         count = len(problems)
         arr, keep, outs = self._problem_array(problems, residual)
-        o = _opts(nb, precision, residual, graph)
+        o = _opts(nb, precision, residual, graph, rotations)
         need = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
                "hsrq_workspace_size_batched")

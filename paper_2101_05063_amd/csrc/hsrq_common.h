@@ -32,7 +32,7 @@ struct ProbDesc {
   long long ldh;
   int n, N, nb, ncols, ld, nblk, m, precision;
   // workspace (device)
-  double *V, *X, *Y, *C, *S, *PHI, *Z0, *Z1;
+  double *V, *X, *Y, *C, *S, *PHI, *Z0, *Z1, *W0, *W1;
   double *BMAX, *VMAX, *BSSQ, *BCMX, *TN, *FIN;
   int32_t *AX, *AMAX;
   // zero-initialised per call: row sums, ||H||_F^2, flags, residual sums

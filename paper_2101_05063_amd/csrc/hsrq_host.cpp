@@ -179,6 +179,8 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.o_PHI = off; off = align_up(off + vec);
     q.o_Z0 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
     q.o_Z1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
+    q.o_W0 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 1) * q.ld);
+    q.o_W1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 1) * q.ld);
     q.o_BMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_VMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_BSSQ = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
@@ -215,6 +217,8 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
     d.PHI = at<double>(work, q.o_PHI);
     d.Z0 = at<double>(work, q.o_Z0);
     d.Z1 = at<double>(work, q.o_Z1);
+    d.W0 = at<double>(work, q.o_W0);
+    d.W1 = at<double>(work, q.o_W1);
     d.BMAX = at<double>(work, q.o_BMAX);
     d.VMAX = at<double>(work, q.o_VMAX);
     d.BSSQ = at<double>(work, q.o_BSSQ);
@@ -361,6 +365,7 @@ bool opts_ok(const hsrq_opts_t* o) {
   if (o->precision != 0 && o->precision != 1) return false;
   if (o->residual != 0 && o->residual != 1) return false;
   if (o->graph < -1 || o->graph > 1) return false;
+  if (o->rotations != 0 && o->rotations != 1) return false;
   return true;
 }
 
@@ -480,7 +485,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
       ProfScope ps(h, HSRQ_K_FAR, a, true);
-      launch_far(P.nb, P.prec, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
+      launch_far(P.nb, P.prec, P.l3rot, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
     }
     hipEventRecord(ev[2 * t], s);
     hipEventRecord(ev[2 * t + 1], a);
@@ -516,6 +521,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
 uint64_t plan_signature(const Plan& P, int count, void* work, bool want_res) {
   Sig g;
   g.add((uint64_t)P.nb);
+  g.add((uint64_t)(P.prec * 2 + P.l3rot));
   g.add((uint64_t)count);
   g.add((uint64_t)reinterpret_cast<uintptr_t>(work));
   g.add((uint64_t)want_res);
@@ -815,6 +821,7 @@ int run_mixed(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* wor
   Plan P2;
   build_plan(P2, (int)q2.size(), q2.data(), nb);
   P2.prec = 0;
+  P2.l3rot = o->rotations;
   void* w2 = at<char>(work, L.o_pass2);
   if (P2.total_bytes > P.total_bytes) return HSRQ_ERR_WORKSPACE;
   if ((st = ensure_sync_events(h, (int)P2.coff.size()))) return st;
@@ -837,6 +844,7 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
   if (o && o->precision == 1) return run_mixed(h, count, probs, work, work_bytes, o);
   Plan P;
   build_plan(P, count, probs, choose_nb(h, count, probs, o));
+  P.l3rot = o ? o->rotations : 0;
   if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
     return HSRQ_ERR_WORKSPACE;
   const bool want_res = wants_residual(o, count, probs);
@@ -1019,6 +1027,7 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
     Plan P;
     build_plan(P, count, problems, nb);
     P.prec = o.precision == 1 ? 1 : 0;
+    P.l3rot = o.rotations;
     if (work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1))) continue;
     if ((st = ensure_sync_events(h, (int)P.coff.size()))) break;
     float t_best = 0.f;

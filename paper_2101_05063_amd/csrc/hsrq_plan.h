@@ -17,7 +17,9 @@ void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStr
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-void launch_far(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
+// l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
+// applied as one product with the folded rotations W; else one at a time
+void launch_far(int nb, int prec, int l3rot, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
@@ -42,13 +44,14 @@ struct ProbPlan {
   Layout lay;
   // byte offsets inside the workspace
   size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
-  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
+  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_W0, o_W1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
   size_t o_zero, o_RSUM, o_HF, o_FLAG, o_RNUM, o_HN;
 };
 
 struct Plan {
   int nb = 64;
-  int prec = 0;  // 1: FP32 tile-update products
+  int prec = 0;    // 1: FP32 tile-update products
+  int l3rot = 0;   // 1: off-diagonal rotations folded and applied on MFMA (opts.rotations)
   std::vector<ProbPlan> pp;
   std::vector<Task> tasks;
   std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges

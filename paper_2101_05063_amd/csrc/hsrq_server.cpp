@@ -285,7 +285,7 @@ int tick(hsrq_server_s* S) {
     if (!crit[pr].empty())
       launch_crit(S->nb, pr, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
-      launch_far(S->nb, pr, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
+      launch_far(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
   }
   hipEventRecord(S->ev_far, a);
   // advance; requests whose last step ran get their final kernels
@@ -580,6 +580,7 @@ int hsrq_server_create(hsrq_server_t* out, int device, size_t hbm_budget_bytes, 
   if (hbm_budget_bytes == 0) return -3;
   if (opts && opts->nb != 0 && opts->nb != 64 && opts->nb != 128) return -4;
   if (opts && opts->precision != 0 && opts->precision != 1) return -4;
+  if (opts && opts->rotations != 0 && opts->rotations != 1) return -4;
   hsrq_server_s* S = new (std::nothrow) hsrq_server_s();
   if (!S) return HSRQ_ERR_ALLOC;
   S->device = device;

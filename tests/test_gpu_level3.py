@@ -1,0 +1,194 @@
+"""GPU parity of the level-3 form of ReduceOffdiag (opts.rotations = 1): the
+rotations of a tile column folded into one matrix W and applied to the
+cross-over columns of the tile rows above as the product H(I, J-) W.
+
+Both forms are backward stable: each computes the solution of a system
+(H + dH - lambda I) x = b with ||dH|| <= c n eps ||H||_F.  They differ only in
+rounding, so the two solutions (and the one-at-a-time reference) agree to
+first order within ||dH|| ||(H - lambda I)^-1|| = c n eps ||H||_F / sigma_min,
+sigma_min the smallest singular value of H - lambda I.  The tests take c = 10
+for the pair (each side's error counted once, with the same headroom as the
+residual bar 10 n eps), compute sigma_min on the host, and require the norm
+and the direction to agree within that bound (never tighter than the direction
+bar 1e-10), the exponent to match unless the norm straddles a power of two
+within the bound, and the flags to match.  For nearly singular systems (shifts
+at eigenvalues) the bound is vacuous and the residual bar is checked instead.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.oracle import columns_of
+from tests.parity import EPS, direction, vec
+from workloads import generators as g
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Solver
+    s = Solver(0)
+    yield s
+    s.close()
+
+
+def dev(A):
+    A = np.asarray(A, dtype=np.float64)
+    return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+
+
+def host(T):
+    return T.t().contiguous().cpu().numpy().T.copy()
+
+
+def run(solver, H, wr, wi, B, rotations, nb=0, residual=False):
+    print(f"[gpu] level-3 n={H.shape[0]} m={len(wr)} nb={nb} rotations={rotations}", flush=True)
+    Y, E, mu, info, res = solver.solve(dev(H), wr, wi, dev(B), nb=nb, residual=residual, rotations=rotations)
+    torch.cuda.synchronize()
+    out = (host(Y), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy())
+    return out + ((res.cpu().numpy(),) if residual else ())
+
+
+def log2norm(E, mu):
+    return E.astype(np.float64) + np.log2(mu)
+
+
+def first_order_bound(H, lam):
+    n = H.shape[0]
+    smin = np.linalg.svd(H - lam * np.eye(n), compute_uv=False)[-1]
+    return 10.0 * n * EPS * np.linalg.norm(H) / smin
+
+
+def check_against(H, wr, wi, got, ref, ctx):
+    Yg, Eg, mug, ig = got[:4]
+    Yr, Er, mur, ir = ref[:4]
+    cols, _ = columns_of(wi)
+    checked = 0
+    for l in range(len(wr)):
+        assert ig[l] == ir[l], (ctx, l, ig[l], ir[l])
+        if ir[l] in (2, 3, 4):
+            continue
+        tol = first_order_bound(H, complex(wr[l], wi[l]))
+        if tol >= 1e-2:
+            continue  # nearly singular: only the residual bar applies
+        checked += 1
+        dl = abs(log2norm(Eg[l:l + 1], mug[l:l + 1])[0] - log2norm(Er[l:l + 1], mur[l:l + 1])[0])
+        assert dl <= 2.0 * tol, (ctx, l, dl, tol)  # |log2(1 + d)| <= 2 d for d <= 1e-2
+        if Eg[l] != Er[l]:
+            lg = log2norm(Er[l:l + 1], mur[l:l + 1])[0]
+            assert abs(Eg[l] - Er[l]) == 1 and abs(lg - round(lg)) <= 2.0 * tol, (ctx, l, Eg[l], Er[l])
+        d = direction(vec(Yg, cols, wi, l), vec(Yr, cols, wi, l))
+        assert 1.0 - d <= max(1e-10, tol), (ctx, l, 1.0 - d, tol)
+    return checked
+
+
+@pytest.mark.parametrize("n,nb", [(129, 64), (200, 64), (333, 128), (700, 64), (700, 128)])
+def test_level3_random_shifts(solver, n, nb):
+    """Shifts inside the spectral radius (the random non-normal H makes most of
+    these systems nearly singular) and outside 1.5 ||H||_2 (well-conditioned:
+    sigma_min >= ||H||_2 / 2, so the bound is informative): level-3 against
+    the reference within the first-order bound."""
+    rng = np.random.default_rng(3000 + n + nb)
+    H = g.random_hessenberg(n, rng)
+    sc = np.abs(np.linalg.eigvals(H)).max()
+    h2 = np.linalg.norm(H, 2)
+    sgn = lambda: 1 if rng.random() < 0.5 else -1
+    wr = list(rng.uniform(-sc, sc, 3)) + [sgn() * rng.uniform(1.5, 2.0) * h2 for _ in range(3)]
+    wi = [0.0] * 6
+    for _ in range(2):
+        wr.append(rng.uniform(-sc, sc))
+        wi.append(rng.uniform(0.1, 1.0) * sc * sgn())
+    r, th = rng.uniform(1.5, 2.0) * h2, rng.uniform(0.2, 1.2)
+    wr.append(r * np.cos(th))
+    wi.append(r * np.sin(th) * sgn())
+    wr, wi = np.array(wr), np.array(wi)
+    B = rng.standard_normal((n, g.ncols(wi)))
+    got = run(solver, H, wr, wi, B, 1, nb=nb)
+    ref = O.batch(H, wr, wi, B)
+    assert check_against(H, wr, wi, got, ref, "oracle") >= 4
+
+
+@pytest.mark.parametrize("n,nb", [(300, 64), (700, 128)])
+def test_level3_eigenvalue_shifts(solver, n, nb):
+    """Host eigenvalues as shifts (nearly singular systems): residual bar for
+    every converged shift, flags as the reference's, and the first-order
+    agreement wherever the bound is informative."""
+    rng = np.random.default_rng(4000 + n)
+    H = g.random_hessenberg(n, rng)
+    ev = np.linalg.eigvals(H)
+    real = ev[np.abs(ev.imag) == 0].real[:8]
+    cplx = ev[ev.imag > 0][:4]
+    wr = np.concatenate([real, cplx.real])
+    wi = np.concatenate([np.zeros(len(real)), cplx.imag])
+    B = np.ones((n, g.ncols(wi)))
+    got = run(solver, H, wr, wi, B, 1, nb=nb, residual=True)
+    ref = O.batch(H, wr, wi, B)
+    check_against(H, wr, wi, got, ref, "oracle")
+    Yg, ig, res = got[0], got[3], got[4]
+    ro = O.residual(H, wr, wi, Yg)
+    conv = ig == 0
+    assert conv.sum() >= len(wr) // 2
+    assert np.all(ro[conv] <= 10 * n * EPS), ro[conv].max()
+    assert np.allclose(res[conv], ro[conv], rtol=0.2, atol=n * EPS)
+
+
+def test_level3_agrees_with_one_at_a_time_c2(solver):
+    """C2 (n = 2000, 150 real + 25 complex-pair eigenvalue shifts): both forms
+    on the GPU; flags equal, residual bar for every converged shift, and the
+    direction bar for the shifts separated by >= 1e-3 ||H||."""
+    c = g.config_c2()
+    H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    n = H.shape[0]
+    a = run(solver, H, wr, wi, B, 0, residual=True)
+    b = run(solver, H, wr, wi, B, 1, residual=True)
+    assert np.array_equal(a[3], b[3])
+    conv = b[3] == 0
+    assert np.all(b[4][conv] <= 10 * n * EPS), b[4][conv].max()
+    cols, _ = columns_of(wi)
+    good = [l for l in range(len(wr)) if c["sep"][l] >= 1e-3 * c["norm2"]]
+    assert len(good) >= 20
+    for l in good:
+        d = direction(vec(a[0], cols, wi, l), vec(b[0], cols, wi, l))
+        assert 1.0 - d <= 1e-10, (l, 1.0 - d)
+
+
+def test_level3_c3(solver):
+    """C3 (n = 8000, m = 1000, graded): the grading makes the rotations of the
+    far tiles nearly (c, s) = (0, +-1), so the two forms round alike almost
+    everywhere: flags and scale exponents bit-exact, mantissas within 1e-12,
+    directions within the bar.  (The one-at-a-time form is bit-identical to
+    the reference's order, so this carries the exact-exponent parity over to
+    the level-3 form on this workload.)"""
+    c = g.config_c3()
+    H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    a = run(solver, H, wr, wi, B, 0)
+    b = run(solver, H, wr, wi, B, 1)
+    assert np.array_equal(a[3], b[3])
+    assert np.array_equal(a[1], b[1])
+    assert np.all(np.abs(b[2] - a[2]) <= 1e-12 * a[2])
+    d = np.abs(np.sum(a[0] * b[0], axis=0)) / (np.linalg.norm(a[0], axis=0) * np.linalg.norm(b[0], axis=0))
+    assert np.all(1.0 - d <= 1e-10), (1.0 - d).max()
+
+
+def test_level3_graph_replay_equals_eager(solver):
+    """The level-3 form under graph replay equals its kernel-by-kernel run."""
+    rng = np.random.default_rng(77)
+    n = 500
+    H = g.random_hessenberg(n, rng)
+    wr, wi = np.array([0.3, -0.7, 1.1]), np.array([0.0, 0.0, 0.4])
+    B = rng.standard_normal((n, g.ncols(wi)))
+    Hd = dev(H)
+    outs = []
+    for graph in (-1, 1, 1):
+        X = dev(B)
+        E, mu, info, _ = solver.dhsrq3(Hd, wr, wi, X, nb=64, graph=graph, rotations=1)
+        torch.cuda.synchronize()
+        outs.append((host(X), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy()))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)

@@ -34,9 +34,9 @@ def host(T):
     return T.t().contiguous().cpu().numpy().T.copy()
 
 
-def run_gpu(solver, H, wr, wi, B, nb=0, residual=False):
-    print(f"[gpu] n={H.shape[0]} m={len(wr)} nb={nb}", flush=True)
-    Y, E, mu, info, res = solver.solve(dev(H), wr, wi, dev(B), nb=nb, residual=residual)
+def run_gpu(solver, H, wr, wi, B, nb=0, residual=False, rotations=0):
+    print(f"[gpu] n={H.shape[0]} m={len(wr)} nb={nb} rotations={rotations}", flush=True)
+    Y, E, mu, info, res = solver.solve(dev(H), wr, wi, dev(B), nb=nb, residual=residual, rotations=rotations)
     torch.cuda.synchronize()
     out = (host(Y), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy())
     if residual:
@@ -57,7 +57,8 @@ def random_shifts(rng, H, nreal, ncplx, neg=False):
 
 
 # ---------------------------------------------------------------------------
-# rotations, diagonal of R and working columns: bit for bit
+# rotations, diagonal of R and working columns: bit for bit when the
+# off-diagonal rotations are applied one at a time (rotations=0, the default)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nb", [64, 128])
 @pytest.mark.parametrize("n", [300, 150, 64, 7])
@@ -66,7 +67,7 @@ def test_rotations_bitwise(solver, n, nb):
     H = g.random_hessenberg(n, rng)
     wr, wi = random_shifts(rng, H, 5, 3, neg=True)
     B = rng.standard_normal((n, g.ncols(wi)))
-    run_gpu(solver, H, wr, wi, B, nb=nb)
+    run_gpu(solver, H, wr, wi, B, nb=nb, rotations=0)
     dv = solver.debug_view(n, wi, nb=nb)
     C, S, PHI, V = (dv[k].cpu().numpy() for k in ("C", "S", "PHI", "V"))
     nbv = dv["nb"]
