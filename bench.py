@@ -491,9 +491,12 @@ def main():
     for kind, fam in (("crit", "k_crit"), ("far", "k_far")):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
-        name = f"hsrq::{fam}<{nbv}, {'true' if args.precision == 1 else 'false'}>"
-        if kind == "far" and args.precision == 0 and args.rotations == 1:
-            name = f"hsrq::k_far3<{nbv}>"
+        f32 = 'true' if args.precision == 1 else 'false'
+        l3 = args.precision == 0 and args.rotations == 1
+        if kind == "far":
+            name = f"hsrq::k_far3<{nbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
+        else:
+            name = f"hsrq::k_crit<{nbv}, {f32}, {'true' if l3 else 'false'}>"
         ach = fl[kind] / (per_solve * 1e-3) / 1e12 if per_solve > 0 else 0.0
         kern[kind] = {"kernel": name, "ms_per_step": round(per_solve, 4),
                       "launches_per_step": launches / args.steps,

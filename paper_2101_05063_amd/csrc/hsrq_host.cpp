@@ -480,7 +480,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s, true);
-      launch_crit(P.nb, P.prec, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
+      launch_crit(P.nb, P.prec, P.l3rot, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
     }
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first

