@@ -254,18 +254,19 @@ def bench_c4(args):
     def problems():
         return [dict(H=H, wr=p["wr"], wi=p["wi"], X=B.clone()) for H, B, p in zip(Hs, Bs, probs_h)]
 
-    best, tune_ms = solver.autotune(problems(), precision=args.precision)
+    best, tune_ms = solver.autotune(problems(), precision=args.precision, rotations=args.rotations)
 
     def timed(graph):
         sets = [problems() for _ in range(args.warmup + args.steps)]
         torch.cuda.synchronize()
         for k in range(args.warmup):
-            solver.batched(sets[k], precision=args.precision, graph=graph)
+            solver.batched(sets[k], precision=args.precision, graph=graph, rotations=args.rotations)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         outs = None
         for k in range(args.steps):
-            outs = solver.batched(sets[args.warmup + k], precision=args.precision, graph=graph)
+            outs = solver.batched(sets[args.warmup + k], precision=args.precision, graph=graph,
+                                  rotations=args.rotations)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps, sets[-1], outs
 
@@ -282,6 +283,7 @@ def bench_c4(args):
                                "4-64 host-eigenvalue shifts each (30% complex pairs), all-ones starts",
                    "matrices": len(probs_h), "sum_n": int(sum(p["H"].shape[0] for p in probs_h)),
                    "shifts": nshift, "columns": ncols, "precision": args.precision,
+                   "rotations": args.rotations,
                    "autotuned_nb": best, "autotune_ms": tune_ms, "graph": args.precision == 0},
         "shifts_per_s": round(nshift / (ms * 1e-3), 2),
         "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
@@ -289,6 +291,7 @@ def bench_c4(args):
     }
     if args.precision == 1:
         line["fallback_shifts"] = fallback
+    if args.precision == 1 or args.rotations == 1:
         line["error_vs_reference"] = error_vs_reference(probs_h, last_set, outs, len(os.sched_getaffinity(0)))
     solver.close()
     print(json.dumps(line), flush=True)
@@ -322,7 +325,8 @@ def bench_c5(args):
     Hd = [torch.from_numpy(np.ascontiguousarray(p["H"].T)).to(dev).t() for p in pool]
     rng = np.random.default_rng(1006)
     reqs = [(b, wr, wi, g.ncols(wi)) for b, wr, wi in g.c5_requests(pool, args.requests + 200)]
-    srv = Server(0, budget_bytes=200 * 10 ** 9, nb=args.nb or 128, precision=args.precision)
+    srv = Server(0, budget_bytes=200 * 10 ** 9, nb=args.nb or 128, precision=args.precision,
+                 rotations=args.rotations)
     keep = {}
 
     def submit(k):
@@ -376,7 +380,7 @@ def bench_c5(args):
         "config": {"workload": "requests on 64 random unreduced Hessenberg matrices, n log-uniform in "
                                "[128, 8192], U{1..n/8} host-eigenvalue shifts (30% complex pairs), all-ones "
                                "starts; HBM budget 200 GB",
-                   "requests": args.requests, "precision": args.precision, "nb": args.nb or 128},
+                   "requests": args.requests, "precision": args.precision, "nb": args.nb or 128, "rotations": args.rotations},
         "p50_ms": round(order_stat(lat, 0.5), 3), "p99_ms": round(order_stat(lat, 0.99), 3),
         "max_ms": round(max(lat), 3),
         "arrival_rate_per_s": round(rate, 2), "saturated_requests_per_s": round(sat, 2),

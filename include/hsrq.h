@@ -275,7 +275,8 @@ int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches
  * arrive while others run join at the next tick.  opts: nb (0 = 128),
  * precision (0 all FP64; 1 FP32 tile products with the FP64 residual check and
  * an FP64 re-solve of the failing shifts, see hsrq_fallback_count), residual
- * (write resid[] when the problem gives it).  Graph replay does not apply.
+ * (write resid[] when the problem gives it), rotations (as for hsrq_dhsrq3).
+ * Graph replay does not apply.
  * Returns HSRQ_ERR_BUSY from submit when the request can never fit (its bytes
  * exceed the budget or its task lists exceed a tick), HSRQ_ERR_ARG for an
  * invalid problem (n < 1, m < 1, missing pointers) or a stopped server.

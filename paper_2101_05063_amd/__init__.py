@@ -251,13 +251,13 @@ class Solver:
         self._keep = keep
         return outs
 
-    def autotune(self, problems, precision=0, stream=None):
+    def autotune(self, problems, precision=0, stream=None, rotations=0):
         """Times each tile size on this problem set and records the fastest in
         the handle (used by later calls with nb=0).  Returns (best_nb,
         {nb: ms}).  The problems' X are not modified."""
         count = len(problems)
         arr, keep, outs = self._problem_array(problems, False)
-        o = _opts(0, precision)
+        o = _opts(0, precision, rotations=rotations)
         need = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
                "hsrq_workspace_size_batched")
@@ -320,7 +320,7 @@ class Server:
     poll() has returned the request's tag."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 200 * 10 ** 9, nb: int = 0, precision: int = 0,
-                 residual: bool = False):
+                 residual: bool = False, rotations: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP library has no CPU fallback")
@@ -328,7 +328,7 @@ class Server:
         self.lib = load_library()
         self.residual = residual
         h = ctypes.c_void_p()
-        o = _opts(nb, precision, residual)
+        o = _opts(nb, precision, residual, rotations=rotations)
         _check(self.lib.hsrq_server_create(ctypes.byref(h), device, int(budget_bytes), ctypes.byref(o)),
                "hsrq_server_create")
         self.h = h

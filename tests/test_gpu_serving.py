@@ -136,3 +136,27 @@ def test_mixed_precision_serving():
     for (H, wr, wi, B), M in zip(reqs, mix):
         Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
         compare(M[0], M[1], M[2], M[3], Yo, Eo, muo, infoo, wi, dir_tol=1e-8, mu_tol=1e-2, straddle_tol=1e-2)
+
+
+def test_level3_serving_alone_equals_mix_and_single_solve():
+    """The serving loop with the level-3 form of ReduceOffdiag (rotations=1):
+    each request's results are bit for bit the same alone, in the mix, and as
+    a single-problem solve with the same options (the arithmetic of a column
+    does not depend on the other columns or requests)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Server, Solver
+    reqs = requests(37, 10, 900)
+    alone = run_alone(Server, reqs, nb=64, rotations=1)
+    mix, _ = run_mix(Server, reqs, nb=64, rotations=1)
+    s = Solver(0)
+    for k, ((H, wr, wi, B), A, M) in enumerate(zip(reqs, alone, mix)):
+        for x, y in zip(A, M):
+            assert np.array_equal(x, y), k
+        X = dev(B)
+        E, mu, info, _ = s.dhsrq3(dev(H), wr, wi, X, nb=64, rotations=1)
+        torch.cuda.synchronize()
+        single = (host(X), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy())
+        for x, y in zip(single, M):
+            assert np.array_equal(x, y), k
+    s.close()
