@@ -82,15 +82,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
 
 
 def load_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter runs, valid
-    only for the kernel sources they were taken on."""
+    """HBM bytes per launch of `kernel` (a name, or names joined by " + " for a
+    family launched as several kernels: launch-weighted) from the committed
+    counter runs, valid only for the kernel sources they were taken on."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     d = json.load(open(TRAFFIC_FILE))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    ks = [d.get("kernels", {}).get(name) for name in kernel.split(" + ")]
+    if any(k is None for k in ks):
+        return None
+    launches = sum(k["launches"] for k in ks)
+    return sum(k["bytes_per_launch"] * k["launches"] for k in ks) / launches if launches else None
 
 
 def _pmc_rows(path):
@@ -500,7 +504,9 @@ def main():
         if kind == "far":
             name = f"hsrq::k_far3<{nbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
         else:
-            name = f"hsrq::k_crit<{nbv}, {f32}, {'true' if l3 else 'false'}>"
+            # steps with many far-tile blocks use the variant that shares its CU
+            tmpl = f"<{nbv}, {f32}, {'true' if l3 else 'false'}>"
+            name = f"hsrq::k_crit{tmpl} + hsrq::k_crit_sh{tmpl}"
         ach = fl[kind] / (per_solve * 1e-3) / 1e12 if per_solve > 0 else 0.0
         kern[kind] = {"kernel": name, "ms_per_step": round(per_solve, 4),
                       "launches_per_step": launches / args.steps,

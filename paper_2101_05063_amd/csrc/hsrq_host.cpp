@@ -480,7 +480,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s, true);
-      launch_crit(P.nb, P.prec, P.l3rot, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
+      launch_crit(P.nb, P.prec, P.l3rot, P.fcnt[t] >= kShareFar, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
     }
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
@@ -882,6 +882,7 @@ int hsrq_create(hsrq_handle_t* out, int device) {
   if (!out) return -1;
   *out = nullptr;
   if (hipSetDevice(device) != hipSuccess) return HSRQ_ERR_HIP;
+  if (crit_smem_init() != 0) return HSRQ_ERR_HIP;
   hsrq_handle_t h = new (std::nothrow) hsrq_handle_s();
   if (!h) return HSRQ_ERR_ALLOC;
   h->device = device;

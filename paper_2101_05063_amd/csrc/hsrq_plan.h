@@ -15,8 +15,14 @@ namespace hsrq {
 
 void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
-void launch_crit(int nb, int prec, int l3rot, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
-                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// allow the critical kernels their dynamic shared memory on the current
+// device (0, or -1 on a HIP error); called once per handle and server
+int crit_smem_init();
+// share: the critical kernel variant that leaves room on its CU for one
+// far-tile block (used for steps with at least kShareFar far-tile blocks)
+constexpr int kShareFar = 512;
+void launch_crit(int nb, int prec, int l3rot, bool share, const ProbDesc* d, const Task* tasks, int ntasks,
+                 hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
 // applied as one product with the folded rotations W; else one at a time
 void launch_far(int nb, int prec, int l3rot, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,

@@ -283,7 +283,7 @@ int tick(hsrq_server_s* S) {
   const ProbDesc* dd = reinterpret_cast<const ProbDesc*>(db);
   for (int pr = 0; pr < 2; ++pr) {
     if (!crit[pr].empty())
-      launch_crit(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
+      launch_crit(S->nb, pr, S->opts.rotations, (int)far[pr].size() >= kShareFar, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
       launch_far(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
   }
@@ -484,6 +484,7 @@ int tick_bytes_estimate(const Req* r, int nb) {
 
 void worker_main(hsrq_server_s* S) {
   int st = hipSetDevice(S->device) == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
+  if (!st && crit_smem_init() != 0) st = HSRQ_ERR_HIP;
   if (!st && hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) st = HSRQ_ERR_HIP;
   if (!st && hipStreamCreateWithFlags(&S->a, hipStreamNonBlocking) != hipSuccess) st = HSRQ_ERR_HIP;
   if (!st && hipMalloc(&S->tick_dev, kTickBytes) != hipSuccess) st = HSRQ_ERR_ALLOC;
