@@ -358,3 +358,112 @@ def test_graded_overflow_is_scaled():
     assert r["info"] in (O.OK, O.NOT_CONVERGED)
     res = O.residual(Hg, np.array([z]), np.array([0.0]), r["y"][:, None])
     assert res[0] <= 10 * n * EPS
+
+
+# ---------------------------------------------------------------------------
+# ||H||_inf and the convergence test of Sec. 4.2, pinned by hand and by exact
+# rational arithmetic on both sides of the threshold
+# ---------------------------------------------------------------------------
+def test_hnorm_inf_hand_computed():
+    """||H||_inf is the largest row sum of |h(i,j)| over the Hessenberg part
+    (Sec. 4.2 uses it in the convergence test).  The entries below the
+    subdiagonal are not part of H and must be ignored; the column sums and the
+    full-matrix row sums give different values, so an oracle that took the
+    1-norm or read the whole array fails."""
+    H = np.array([[1.0, -2.0, 0.5, 3.0],
+                  [4.0, 1.0, -1.0, 0.0],
+                  [9.0, -0.25, 2.0, -6.0],
+                  [7.0, 5.0, 0.5, 1.0]])
+    # Hessenberg row sums: 6.5, 6, 0.25 + 2 + 6 = 8.25, 0.5 + 1 = 1.5
+    assert O.hnorm_inf(H) == 8.25
+    # the alternatives it must not be: Hessenberg column sums 5, 3.25, 4, 10;
+    # full-matrix row sums 6.5, 6, 17.25, 13.5
+    assert O.hnorm_inf(H.T.copy()) != 8.25
+
+
+def _exact_hessenberg_solve(H, lam, b):
+    """(H - lam I) x = b in exact rational arithmetic, reading only the
+    Hessenberg part of H (Gaussian elimination, no pivoting needed: the
+    systems used here have a nonzero leading pivot after the row swaps of
+    partial pivoting, which is done exactly)."""
+    n = H.shape[0]
+    A = [[Fraction(float(H[i, j])) if j >= i - 1 else Fraction(0) for j in range(n)] for i in range(n)]
+    for i in range(n):
+        A[i][i] -= Fraction(float(lam))
+    x = [Fraction(float(v)) for v in b]
+    for k in range(n):
+        p = max(range(k, n), key=lambda r: abs(A[r][k]))
+        A[k], A[p] = A[p], A[k]
+        x[k], x[p] = x[p], x[k]
+        for r in range(k + 1, n):
+            f = A[r][k] / A[k][k]
+            if f:
+                for j in range(k, n):
+                    A[r][j] -= f * A[k][j]
+                x[r] -= f * x[k]
+    for k in range(n - 1, -1, -1):
+        x[k] = (x[k] - sum(A[k][j] * x[j] for j in range(k + 1, n))) / A[k][k]
+    return x
+
+
+def threshold_system(k):
+    """A 3 x 3 unreduced Hessenberg matrix whose solve is nearly exact in
+    floating point: h(3,3) equals the shift and h(2,3) = 0, so both rotations
+    are (c, s) = (0, -1), R(1,1) = delta = h(1,3) = k 2^-52 and the solution
+    is (-4/3, 0, 7 / (3 delta)); the entry below the subdiagonal (100) is not
+    part of H.  ||H||_inf = 7 (row 2),
+    ||H||_1 = 6.5, ||H||_F = sqrt(32.5 + delta^2); b = (3, 4, 0) has
+    ||b||_2 = 5, ||b||_inf = 4, ||b||_1 = 7."""
+    delta = k * 2.0 ** -52
+    H = np.array([[1.0, -2.0, delta],
+                  [-3.0, 4.0, 0.0],
+                  [100.0, 0.5, 1.5]])
+    return H, 1.5, np.array([3.0, 4.0, 0.0])
+
+
+def test_convergence_threshold_both_sides():
+    """Converged iff ||x_true||_2 / ||b||_2 >= 1 / (10 n eps ||H||_inf) with
+    eps = 2^-52 (Sec. 4.2 with the starting vector's norm made explicit).
+    The exact solution (rational arithmetic) places the ratio 1% above the
+    threshold for one delta and 1% below it for another; the reference must
+    flag the first converged and the second not.  Each plausible misreading
+    (1-norm or Frobenius norm of H, entries below the subdiagonal counted,
+    n instead of 10 n, eps = 2^-53, another norm of b) moves the threshold by
+    more than 1% and misclassifies one of the two cases, which the test also
+    checks against the exact ratios."""
+    n = 3
+    eps = Fraction(1, 2 ** 52)
+
+    def ratio_sq(k):
+        H, lam, b = threshold_system(k)
+        x = _exact_hessenberg_solve(H, lam, b)
+        return sum(v * v for v in x) / sum(Fraction(float(v)) ** 2 for v in b)
+
+    T_sq = 1 / (10 * n * eps * 7) ** 2
+    # the ratio falls as delta = k 2^-52 grows; the boundary lies near
+    # k = 7 / 15 * 210 = 98
+    k_lo = max(k for k in range(50, 200) if ratio_sq(k) >= Fraction(101, 100) ** 2 * T_sq)
+    k_hi = min(k for k in range(50, 200) if ratio_sq(k) <= Fraction(99, 100) ** 2 * T_sq)
+    assert k_lo < k_hi <= k_lo + 6
+    for k, want in ((k_lo, O.OK), (k_hi, O.NOT_CONVERGED)):
+        H, lam, b = threshold_system(k)
+        r = O.solve1(H, lam, b)
+        assert r["info"] == want, (k, r["info"])
+        x = np.array([float(v) for v in _exact_hessenberg_solve(H, lam, b)])
+        assert abs(r["mu"] * 2.0 ** r["E"] / np.linalg.norm(x) - 1.0) < 1e-14
+        assert direction(r["y"], x) > 1.0 - 1e-15
+    # sensitivity: each misreading's threshold classifies one case wrongly
+    nb2, nbi, nb1 = Fraction(25), Fraction(16), Fraction(49)
+    wrong = {
+        "1-norm of H": (Fraction(13, 2), 10 * n, eps, nb2),
+        "Frobenius norm of H": (Fraction(5.70087712549569), 10 * n, eps, nb2),
+        "entries below the subdiagonal": (Fraction(102), 10 * n, eps, nb2),
+        "n instead of 10 n": (Fraction(7), n, eps, nb2),
+        "eps = 2^-53": (Fraction(7), 10 * n, eps / 2, nb2),
+        "max-norm of b": (Fraction(7), 10 * n, eps, nbi),
+        "1-norm of b": (Fraction(7), 10 * n, eps, nb1),
+    }
+    for what, (hn, nn, ee, bb) in wrong.items():
+        t_sq = 1 / (nn * ee * hn) ** 2
+        conv = [ratio_sq(k) * nb2 / bb >= t_sq for k in (k_lo, k_hi)]
+        assert conv != [True, False], what
