@@ -48,7 +48,8 @@ def table1_flops(n, nb, wi):
     Returns a dict: far (off-diagonal tiles not adjacent to the diagonal:
     the far-tile kernel), crit (superdiagonal tiles + diagonal tiles: the
     critical kernel), update (the level-3 part: Update of every
-    off-diagonal tile), total."""
+    off-diagonal tile), far_update (the Update of the tiles in the far-tile
+    kernel), total."""
     import numpy as np
     N = (n + nb - 1) // nb
     ends = [n - (N - 1 - t) * nb for t in range(N)]
@@ -65,8 +66,9 @@ def table1_flops(n, nb, wi):
     far = nb * far_rows * (per_r * nreal + per_c * ncplx)
     crit = nb * super_rows * (per_r * nreal + per_c * ncplx) + diag2 * (diag_r * nreal + diag_c * ncplx)
     update = nb * (far_rows + super_rows) * (2.0 * nreal + 4.0 * ncplx)
+    far_update = nb * far_rows * (2.0 * nreal + 4.0 * ncplx)
     back = 6.0 * (n - 1) * nreal + 20.0 * (n - 1) * ncplx
-    return dict(far=far, crit=crit, update=update, total=far + crit + back)
+    return dict(far=far, crit=crit, update=update, far_update=far_update, total=far + crit + back)
 
 
 def kernel_source_hash():
@@ -158,29 +160,65 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
 
 
-def cpu_baseline(c, seconds, cores):
-    """The plain C reference on a bounded sample of the same shifts: passes
-    over leading shifts of the list, sized so that the sample takes about
-    `seconds` of wall time on `cores` threads (the whole list is used, more
-    than once if one pass is shorter than that)."""
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_reference_c3(c, seconds, cores):
+    """The plain C reference on the C3 shifts, on `cores` threads: all of them
+    when that is expected to take at most `seconds`, else a stratified subset
+    (every k-th shift of the list, so that the sample spans the whole range of
+    eigenvalues and exponents).  The expectation comes from a probe of
+    `cores` shifts spread over the list.  Returns (cpu_baseline dict, sample
+    indices, reference outputs on the sample)."""
+    import numpy as np
+
     from oracle import oracle as O
     H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    m = len(wr)
     O.build()
-    k = max(1, cores)
+    probe = np.linspace(0, m - 1, max(1, cores)).round().astype(int)
     t0 = time.perf_counter()
-    O.batch(H, wr[:k], wi[:k], B[:, :k], nthreads=cores)
-    per_round = max(time.perf_counter() - t0, 1e-3)
-    want = max(1, int(seconds / per_round)) * k
-    done, dt = 0, 0.0
+    O.batch(H, wr[probe], wi[probe], B[:, probe], nthreads=cores)
+    per_shift = max(time.perf_counter() - t0, 1e-3) / len(probe)
+    k = max(1, int(np.ceil(m * per_shift / seconds)))
+    sel = np.arange(0, m, k)
     t0 = time.perf_counter()
-    while done < want:
-        s = min(len(wr), want - done)
-        O.batch(H, wr[:s], wi[:s], B[:, :s], nthreads=cores)
-        done += s
+    Yo, Eo, muo, infoo = O.batch(H, wr[sel], wi[sel], B[:, sel], nthreads=cores)
     dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="eigenvectors/s", cores=cores, kind="oracle",
-                sample=f"{done} solves over the leading shifts of the {len(wr)}-shift list (n={H.shape[0]}), "
-                       f"{dt:.1f} s wall on {cores} threads")
+    base = dict(value=len(sel) / dt, unit="eigenvectors/s", cores=cores, kind="oracle", cpu_model=cpu_model(),
+                sample=(f"all {m} shifts of the C3 workload (n={H.shape[0]})" if k == 1 else
+                        f"{len(sel)} of the {m} C3 shifts (every {k}th, n={H.shape[0]})") +
+                       f", {dt:.1f} s wall on {cores} threads")
+    return base, sel, (Yo, Eo, muo, infoo)
+
+
+def error_vs_reference_c3(Yg, Eg, mug, infog, sel, ref, wi):
+    """Per-result error of one C3 solve against the reference on the sampled
+    shifts: flags, exponents (binade straddles within 1e-6 in log2 reported
+    apart), mantissas, directions."""
+    import numpy as np
+    Yo, Eo, muo, infoo = ref
+    Eg, mug, infog = Eg[sel], mug[sel], infog[sel]
+    Yg = Yg[:, sel]
+    d = np.abs(np.sum(Yg * Yo, axis=0)) / (np.linalg.norm(Yg, axis=0) * np.linalg.norm(Yo, axis=0))
+    same = Eg == Eo
+    lg = Eo + np.log2(np.where(muo > 0, muo, 1.0))
+    straddle = (~same) & (np.abs(Eg - Eo) == 1) & (np.abs(lg - np.round(lg)) < 1e-6)
+    rel = np.abs(mug[same] - muo[same]) / muo[same]
+    return {"results": int(len(sel)), "flag_mismatches": int(np.sum(infog != infoo)),
+            "exponent_mismatches": int(np.sum(~same & ~straddle)),
+            "exponent_binade_straddles": int(np.sum(straddle)),
+            "max_rel_mantissa_diff": float(rel.max()) if rel.size else 0.0,
+            "median_rel_mantissa_diff": float(np.median(rel)) if rel.size else 0.0,
+            "max_1_minus_cos": float(max(0.0, (1.0 - d).max()))}
 
 
 def error_vs_reference(probs_h, probs_d, outs, cores):
@@ -309,15 +347,15 @@ def order_stat(x, q):
     return xs[max(0, math.ceil(q * len(xs)) - 1)]
 
 
-def bench_c5(args):
+def serving_run(args, requests, warm):
     """Serving: requests on a pool of 64 random unreduced Hessenberg matrices
     (n log-uniform in [128, 8192]), each with U{1..n/8} host-eigenvalue shifts
     (30% complex pairs) and all-ones starts, H resident on the device.  First
-    the saturated throughput is measured closed-loop (a burst of requests
-    submitted at once); then --requests arrivals follow a Poisson process at
-    0.7 times that rate, submitted to the library's serving loop (HBM budget
-    200 GB) as they arrive.  Latency = completion - arrival on the server's
-    clock; p50/p99 are exact order statistics."""
+    the saturated throughput is measured closed-loop (`warm` requests
+    submitted at once after a warm-up of 20); then `requests` arrivals follow
+    a Poisson process at 0.7 times that rate, submitted to the library's
+    serving loop (HBM budget 200 GB) as they arrive.  Latency = completion -
+    arrival on the server's clock; p50/p99 are exact order statistics."""
     import numpy as np
     import torch
 
@@ -328,7 +366,7 @@ def bench_c5(args):
     dev = torch.device("cuda:0")
     Hd = [torch.from_numpy(np.ascontiguousarray(p["H"].T)).to(dev).t() for p in pool]
     rng = np.random.default_rng(1006)
-    reqs = [(b, wr, wi, g.ncols(wi)) for b, wr, wi in g.c5_requests(pool, args.requests + 200)]
+    reqs = [(b, wr, wi, g.ncols(wi)) for b, wr, wi in g.c5_requests(pool, requests + warm)]
     srv = Server(0, budget_bytes=200 * 10 ** 9, nb=args.nb or 128, precision=args.precision,
                  rotations=args.rotations)
     keep = {}
@@ -337,35 +375,38 @@ def bench_c5(args):
         b, wr, wi, nc = reqs[k]
         n = Hd[b].shape[0]
         X = torch.ones((nc, n), dtype=torch.float64, device=dev).t()
+        # the server waits for the fill on torch's stream before it reads X
         keep[k] = (X, srv.submit(Hd[b], wr, wi, X, k))
 
-    # warm-up and saturated throughput (closed loop: 200 requests at once)
-    for k in range(20):
+    # warm-up and saturated throughput (closed loop: the rest of the warm
+    # requests at once)
+    w0 = min(20, warm // 2)
+    for k in range(w0):
         submit(k)
     done = {}
-    while len(done) < 20:
+    while len(done) < w0:
         for c in srv.poll(wait_ms=20):
             done[c["tag"]] = c
     t0 = srv.clock()
-    for k in range(20, 200):
+    for k in range(w0, warm):
         submit(k)
-    while len(done) < 200:
+    while len(done) < warm:
         for c in srv.poll(wait_ms=20):
             done[c["tag"]] = c
-    sat = 180 / (srv.clock() - t0)
+    sat = (warm - w0) / (srv.clock() - t0)
     rate = 0.7 * sat
     # open loop, Poisson arrivals
-    gaps = rng.exponential(1.0 / rate, args.requests)
+    gaps = rng.exponential(1.0 / rate, requests)
     arrive = np.cumsum(gaps)
     t0 = srv.clock()
     nxt, recs = 0, {}
     keep.clear()
-    while len(recs) < args.requests:
+    while len(recs) < requests:
         now = srv.clock() - t0
-        while nxt < args.requests and arrive[nxt] <= now:
-            submit(200 + nxt)
+        while nxt < requests and arrive[nxt] <= now:
+            submit(warm + nxt)
             nxt += 1
-        wait = 5 if nxt >= args.requests else max(0, min(5, int((arrive[nxt] - now) * 1e3)))
+        wait = 5 if nxt >= requests else max(0, min(5, int((arrive[nxt] - now) * 1e3)))
         for c in srv.poll(wait_ms=wait):
             recs[c["tag"]] = c
             keep.pop(c["tag"], None)
@@ -376,15 +417,11 @@ def bench_c5(args):
     status_bad = sum(1 for c in recs.values() if c["status"] != 0)
     fb = sum(c["fallback"] for c in recs.values())
     srv.close()
-    line = {
-        "metric": "serving p50/p99 request latency (Poisson arrivals at 0.7x saturated throughput)",
-        "value": round(order_stat(lat, 0.99), 3), "unit": "ms (p99)", "n_gpus": 1,
-        "steps": args.requests, "warmup": 200, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
-        "config": {"workload": "requests on 64 random unreduced Hessenberg matrices, n log-uniform in "
-                               "[128, 8192], U{1..n/8} host-eigenvalue shifts (30% complex pairs), all-ones "
-                               "starts; HBM budget 200 GB",
-                   "requests": args.requests, "precision": args.precision, "nb": args.nb or 128, "rotations": args.rotations},
+    out = {
+        "workload": "requests on 64 random unreduced Hessenberg matrices, n log-uniform in [128, 8192], "
+                    "U{1..n/8} host-eigenvalue shifts (30% complex pairs), all-ones starts; HBM budget 200 GB",
+        "requests": requests, "warmup": warm, "precision": args.precision, "nb": args.nb or 128,
+        "rotations": args.rotations,
         "p50_ms": round(order_stat(lat, 0.5), 3), "p99_ms": round(order_stat(lat, 0.99), 3),
         "max_ms": round(max(lat), 3),
         "arrival_rate_per_s": round(rate, 2), "saturated_requests_per_s": round(sat, 2),
@@ -392,7 +429,23 @@ def bench_c5(args):
         "failed_requests": status_bad,
     }
     if args.precision == 1:
-        line["fallback_shifts"] = fb
+        out["fallback_shifts"] = fb
+    return out
+
+
+def bench_c5(args):
+    """The serving workload alone (see serving_run), as its own JSON line."""
+    sv = serving_run(args, args.requests, 200)
+    line = {
+        "metric": "serving p50/p99 request latency (Poisson arrivals at 0.7x saturated throughput)",
+        "value": sv["p99_ms"], "unit": "ms (p99)", "n_gpus": 1,
+        "steps": args.requests, "warmup": 200, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": sv["workload"], "requests": args.requests, "precision": args.precision,
+                   "nb": sv["nb"], "rotations": args.rotations},
+    }
+    line.update({k: v for k, v in sv.items() if k not in ("workload", "requests", "warmup", "precision", "nb",
+                                                         "rotations")})
     print(json.dumps(line), flush=True)
 
 
@@ -412,6 +465,10 @@ def main():
                     help="c3: the headline single-matrix solve; c4: 512 matrices of uneven order in one "
                          "graph launch (batching); c5: the serving loop under Poisson arrivals")
     ap.add_argument("--requests", type=int, default=2000, help="c5: open-loop arrivals")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="c3: Poisson arrivals of the serving sub-measurement (0 = skip it)")
+    ap.add_argument("--one-form", action="store_true",
+                    help="c3: time only the form given by --rotations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -448,11 +505,87 @@ def main():
     Bd = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev).t()
     solver = Solver(0)
     nb = args.nb
+    # the tile size the library chooses (same rule as the host planner)
+    nbv = nb if nb in (64, 128) else (128 if n >= 2048 else 64)
+    fl = table1_flops(n, nbv, wi)
+    forms = [args.rotations] + ([1 - args.rotations] if args.precision == 0 and not args.one_form else [])
+    res = {rot: run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rot, fl, args) for rot in forms}
+    head = res[args.rotations]
+    ms, kern = head["ms"], head["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    dk = kern[dom]
+    roof = {"kernel": dk["kernel"], "bound": "alu", "achieved": dk["achieved_tflops"],
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": dk["frac_fp64_peak"],
+            "traffic": load_traffic(dk["kernel"]),
+            "avg_launch_ms": dk["avg_launch_ms"], "launches_per_step": dk["launches_per_step"],
+            "flops_per_launch": dk["flops_per_launch"]}
+    line = {
+        "metric": "eigenvectors/s (n=8000, m=1000; + % FP64 MFMA peak of the level-3 update)",
+        "value": round(m / (ms * 1e-3), 2), "unit": "eigenvectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": "graded random unreduced Hessenberg n=8000, 1000 real eigenvalue shifts, "
+                               "all-ones starts (D_ii = 10^(300 i/n))",
+                   "n": n, "m": m, "nb": nbv, "precision": args.precision, "rotations": args.rotations,
+                   "graph": head["graph"]},
+        "ms_per_step_kernel_by_kernel": head["ms_eager"],
+        "ms_per_step_with_kernel_events": head["ms_prof"],
+        "roofline": roof,
+        "kernels": kern,
+        "level3_update": head["update"],
+        "path_tflops": round(fl["total"] / (ms * 1e-3) / 1e12, 3),
+        "phases_ms_per_step": head["phases"],
+        "converged_fraction": head["converged_fraction"],
+        "scale_exp_range": head["scale_exp_range"],
+    }
+    if args.precision == 1:
+        line["fallback_shifts"] = solver.fallback_count()
+    for rot in forms[1:]:
+        o = res[rot]
+        line["one_at_a_time_form" if rot == 0 else "level3_form"] = {
+            "rotations": rot, "value": round(m / (o["ms"] * 1e-3), 2), "unit": "eigenvectors/s",
+            "ms_per_step": o["ms"], "ms_per_step_kernel_by_kernel": o["ms_eager"], "kernels": o["kernels"],
+            "level3_update": o["update"], "converged_fraction": o["converged_fraction"]}
+    solver.close()
+    if not args.no_cpu_baseline:
+        cores = len(os.sched_getaffinity(0))
+        base, sel, ref = cpu_reference_c3(c, args.cpu_seconds, cores)
+        line["cpu_baseline"] = base
+        # every form's results against the reference on the same sample
+        err = {}
+        for rot in forms:
+            o = res[rot]
+            err[f"rotations={rot}"] = error_vs_reference_c3(o["Y"], o["E"], o["mu"], o["info"], sel, ref, wi)
+        line["error_vs_reference"] = err
+    if args.serving_requests > 0 and args.precision == 0:
+        line["serving"] = serving_run(args, args.serving_requests, 100)
+    print(json.dumps(line), flush=True)
+
+
+def mfma_counters():
+    """MFMA-busy fractions per kernel from the committed counter run (valid
+    only for the kernel sources it was taken on), or {}."""
+    path = os.path.join(ROOT, "profiles", "mfma_c3.json")
+    if not os.path.exists(path):
+        return {}
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return {}
+    return d.get("kernels", {})
+
+
+def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
+    """K solves of C3 in one form of ReduceOffdiag, timed three ways: replayed
+    from the library's captured graph (the figure reported), kernel by
+    kernel, and kernel by kernel with HIP timing events attached to every
+    step-kernel dispatch (the kernel durations)."""
+    import numpy as np
+    import torch
+    m, n = len(wr), Hd.shape[0]
     # preallocate every in/out buffer: the timed regions hold solves only
     Xw = [Bd.clone() for _ in range(max(args.warmup, 1))]
     Xs = [Bd.clone() for _ in range(args.steps)]
-    # the headline: K solves replayed from the library's captured graph (the
-    # FP32 variant is launched kernel by kernel: it has a host decision inside)
+    # the FP32 variant is launched kernel by kernel: it has a host decision inside
     graph = 1 if args.precision == 0 else -1
 
     def timed(graph, prof):
@@ -462,8 +595,7 @@ def main():
             A.copy_(Bd)
         torch.cuda.synchronize()
         for k in range(args.warmup):
-            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph,
-                          rotations=args.rotations)
+            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph, rotations=rotations)
         torch.cuda.synchronize()
         if prof:
             solver.profile(True)
@@ -473,7 +605,7 @@ def main():
         outs = []
         for k in range(args.steps):
             outs.append(solver.dhsrq3(Hd, wr, wi, Xs[k], nb=nb, precision=args.precision, graph=graph,
-                                      rotations=args.rotations))
+                                      rotations=rotations))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pr = None
@@ -483,24 +615,16 @@ def main():
         return (t1 - t0) * 1e3 / args.steps, outs, pr
 
     ms, outs, _ = timed(graph, False)
-    # the same K solves kernel by kernel, once plain and once with HIP timing
-    # events attached to every step-kernel dispatch (their durations give the
-    # roofline); the events cost a few per cent, hence the separate passes
+    E, mu, info = (t.cpu().numpy() for t in outs[-1][:3])
+    Y = Xs[-1].t().contiguous().cpu().numpy().T
     ms_eager, _, _ = timed(-1, False)
     ms_prof, _, prof = timed(-1, True)
-    info = outs[-1][2].cpu().numpy()
-    E = outs[-1][0].cpu().numpy()
-    conv = float((info == 0).mean())
-
-    # the tile size the library chose (same rule as the host planner)
-    nbv = nb if nb in (64, 128) else (128 if n >= 2048 else 64)
-    fl = table1_flops(n, nbv, wi)
+    l3 = args.precision == 0 and rotations == 1
+    f32 = "true" if args.precision == 1 else "false"
     kern = {}
-    for kind, fam in (("crit", "k_crit"), ("far", "k_far")):
+    for kind in ("crit", "far"):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
-        f32 = 'true' if args.precision == 1 else 'false'
-        l3 = args.precision == 0 and args.rotations == 1
         if kind == "far":
             name = f"hsrq::k_far3<{nbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
         else:
@@ -513,43 +637,23 @@ def main():
                       "avg_launch_ms": round(ms_k / launches, 5) if launches else None,
                       "flops_per_launch": fl[kind] / (launches / args.steps) if launches else None,
                       "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK_FP64_TFLOPS, 4)}
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    dk = kern[dom]
-    roof = {"kernel": dk["kernel"], "bound": "alu", "achieved": dk["achieved_tflops"],
-            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": dk["frac_fp64_peak"],
-            "traffic": load_traffic(dk["kernel"]),
-            "avg_launch_ms": dk["avg_launch_ms"], "launches_per_step": dk["launches_per_step"],
-            "flops_per_launch": dk["flops_per_launch"]}
-    value = m / (ms * 1e-3)
-    tile_ms = (prof["far"][0] + prof["crit"][0]) / args.steps
-    line = {
-        "metric": "eigenvectors/s (n=8000, m=1000; + % FP64 MFMA peak of the level-3 update)",
-        "value": round(value, 2), "unit": "eigenvectors/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
-        "config": {"workload": "graded random unreduced Hessenberg n=8000, 1000 real eigenvalue shifts, "
-                               "all-ones starts (D_ii = 10^(300 i/n))",
-                   "n": n, "m": m, "nb": nbv, "precision": args.precision, "rotations": args.rotations,
-                   "graph": graph == 1},
-        "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
-        "ms_per_step_with_kernel_events": round(ms_prof, 4),
-        "roofline": roof,
-        "kernels": kern,
-        "level3_update": {"flops": fl["update"],
-                          "frac_fp64_mfma_peak_over_tile_kernel_time":
-                              round(fl["update"] / (tile_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)},
-        "path_tflops": round(fl["total"] / (ms * 1e-3) / 1e12, 3),
-        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
-        "converged_fraction": conv,
-        "scale_exp_range": [int(E.min()), int(E.max())],
-    }
-    if args.precision == 1:
-        line["fallback_shifts"] = solver.fallback_count()
-    if not args.no_cpu_baseline:
-        cores = len(os.sched_getaffinity(0))
-        line["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, cores)
-    solver.close()
-    print(json.dumps(line), flush=True)
+    # the level-3 update in the far-tile kernel: its matrix-core flops (the
+    # update product, and in the level-3 form also the rotation product with
+    # the same H tile) over that kernel's own time
+    far_ms = prof["far"][0] / args.steps
+    mfma = fl["far_update"] * (2.0 if l3 else 1.0)
+    upd = {"kernel": kern["far"]["kernel"], "update_flops_per_step": fl["update"],
+           "far_kernel_mfma_flops_per_step": mfma,
+           "far_kernel_mfma_tflops": round(mfma / (far_ms * 1e-3) / 1e12, 3) if far_ms > 0 else None,
+           "frac_fp64_mfma_peak": round(mfma / (far_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4) if far_ms > 0 else None}
+    cnt = mfma_counters().get(kern["far"]["kernel"])
+    if cnt:
+        upd["mfma_busy_from_counters"] = cnt.get("mfma_busy")
+    return {"ms": round(ms, 4), "ms_eager": round(ms_eager, 4), "ms_prof": round(ms_prof, 4), "graph": graph == 1,
+            "kernels": kern, "update": upd,
+            "phases": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+            "converged_fraction": float((info == 0).mean()),
+            "scale_exp_range": [int(E.min()), int(E.max())], "Y": Y, "E": E, "mu": mu, "info": info}
 
 
 if __name__ == "__main__":

@@ -71,9 +71,10 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 set if it ran on the handle, else 128 when the largest
  *                 order is >= 2048 and 64 otherwise.
  *   Any other value of nb, precision (0, 1), residual (0, 1), graph
- *   (-1, 0, 1) or rotations (0, 1) makes the call fail with the position of opts (LAPACK style:
- *   -16 for hsrq_dhsrq3, -5 for hsrq_workspace_size) or HSRQ_ERR_ARG for the
- *   batched, tuning and debug calls; nothing is substituted silently.
+ *   (-1, 0, 1), rotations (0, 1) or share_min_far (>= -1) makes the call
+ *   fail with the position of opts (LAPACK style: -16 for hsrq_dhsrq3, -5
+ *   for hsrq_workspace_size) or HSRQ_ERR_ARG for the batched, tuning and
+ *   debug calls; nothing is substituted silently.
  *   cols_per_block reserved (shift blocks are fixed by the kernels: 64
  *                 columns per far-tile block, 16 per critical block).
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
@@ -87,6 +88,12 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 kernel by kernel; 0 = default (graph for batched calls,
  *                 kernel by kernel for single calls).  Profiling forces
  *                 kernel-by-kernel launches.
+ *   share_min_far the critical kernel of a tile-column step comes in two
+ *                 variants that compute the same bits: one that takes a
+ *                 compute unit to itself and one that leaves room on it for
+ *                 one far-tile block.  Steps with at least share_min_far
+ *                 far-tile blocks use the second.  0 = the library's default
+ *                 (512), -1 = never; any value >= -1 is accepted.
  *   rotations     how the rotations of a tile column reach the cross-over
  *                 columns of the tile rows above its superdiagonal tile
  *                 (ReduceOffdiag, Sec. 3.1): 0 = one rotation at a time in
@@ -107,7 +114,8 @@ typedef struct {
     int residual;
     int graph;
     int rotations;
-    int reserved[2];
+    int share_min_far;
+    int reserved;
 } hsrq_opts_t;
 
 /* One problem of a batched call.  H, X, scale_exp, scale_mant, info and
@@ -175,6 +183,48 @@ int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh,
                 double* resid, void* work, size_t work_bytes,
                 const hsrq_opts_t* opts);
 
+/*
+ * Inverse iteration with restarts (HSRQ3IN, Sec. 4.2, Algorithm 14, with
+ * the grouping of Algorithm 15): every shift is solved from the starting
+ * vector S(:, 0); the shifts that fail the convergence test are solved again
+ * from S(:, 1), those that fail again from S(:, 2), and so on up to S(:,
+ * ntries - 1), each try one hsrq_dhsrq3 of the shifts still open.  A complex
+ * shift starts from the real vector S(:, t) (imaginary part zero).  The paper
+ * takes each new starting vector orthogonal to the previous ones; the caller
+ * supplies them, so that the same vectors can be given to any other
+ * implementation.  Shifts are processed in groups of consecutive shifts
+ * (a complex shift's two columns never split) with as many columns as the
+ * workspace holds (Algorithm 15's w_max is work_bytes), so a small workspace
+ * bounds the memory at the cost of more launches.
+ *
+ *   n, H, ldh, m, wr, wi   as for hsrq_dhsrq3                        2-7
+ *   S, lds       device, n x ntries starting vectors, lds >= n         8, 9
+ *   ntries       tries per shift (>= 1)                                10
+ *   X, ldx       device, n x ncols, out only: the unit vectors of the last
+ *                try of each shift, caller column layout               11, 12
+ *   scale_exp, scale_mant, info   device, length m, as for hsrq_dhsrq3,
+ *                of the returned try (info 1: no try converged)        13-15
+ *   tries        device, length m, or NULL: the 0-based try whose result
+ *                is returned                                           16
+ *   resid        device, length m, or NULL (opts.residual)             17
+ *   work, work_bytes  device workspace, 256-byte aligned; at least the
+ *                bytes of a group of one shift (two columns if any shift
+ *                is complex), at most hsrq_hsrq3in_workspace_size      18, 19
+ *   opts         as for hsrq_dhsrq3; precision must be 0               20
+ * The call synchronises the handle's stream once per try and group (the
+ * flags decide the next try) and returns when the last try has been
+ * enqueued.
+ */
+int hsrq_hsrq3in_workspace_size(hsrq_handle_t h, int n, int m, const double* wi,
+                                const hsrq_opts_t* opts, size_t* bytes);
+int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
+                 int m, const double* wr, const double* wi,
+                 const double* S, int lds, int ntries,
+                 double* X, int ldx,
+                 int32_t* scale_exp, double* scale_mant, int32_t* info,
+                 int32_t* tries, double* resid, void* work, size_t work_bytes,
+                 const hsrq_opts_t* opts);
+
 /* Workspace query for hsrq_dhsrq3_batched (problems: host array of count
    descriptors; only n, m and wi are read). */
 int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
@@ -226,6 +276,17 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
                   const hsrq_opts_t* opts, int* best_nb, double* ms);
 
 /*
+ * Tuner cache.  hsrq_autotune_save writes the handle's tuned choices (one per
+ * problem-set signature) to the text file at path (host string);
+ * hsrq_autotune_load merges a file written by hsrq_autotune_save into the
+ * handle (an entry replaces one with the same signature), so that a later
+ * process skips the timing runs.  HSRQ_ERR_ARG if the file cannot be opened
+ * or is malformed (then nothing is merged).
+ */
+int hsrq_autotune_save(hsrq_handle_t h, const char* path);
+int hsrq_autotune_load(hsrq_handle_t h, const char* path);
+
+/*
  * Debug/parity view of the workspace after a single-problem call: device
  * pointers to the recorded rotations (c, s and the diagonal of R; row k,
  * column c at [k * ld + c], internal column order) and the final working
@@ -267,7 +328,11 @@ int hsrq_profile_read(hsrq_handle_t h, int nkinds, double* ms, int64_t* launches
  *
  * hsrq_server_submit queues one problem (H and X device-resident, owned by
  * the caller and kept alive until its completion is polled; wr and wi are
- * copied).  Requests are admitted in arrival order while the sum of their
+ * copied).  stream (a hipStream_t; NULL is the null stream) is the stream on
+ * which the caller produced H and X: the server's kernels for the request
+ * wait for every piece of work enqueued on it before the call (an event
+ * recorded on it at submission).  Requests are admitted in arrival order
+ * while the sum of their
  * device bytes (workspace, which the server allocates from its own pool, plus
  * H and X) stays within hbm_budget_bytes.  Every admitted request advances one
  * tile-column step per tick; a tick is one critical and one far-tile launch
@@ -300,7 +365,7 @@ typedef struct {
 } hsrq_completion_t;
 
 int hsrq_server_create(hsrq_server_t* out, int device, size_t hbm_budget_bytes, const hsrq_opts_t* opts);
-int hsrq_server_submit(hsrq_server_t server, const hsrq_problem_t* problem, uint64_t tag);
+int hsrq_server_submit(hsrq_server_t server, const hsrq_problem_t* problem, uint64_t tag, void* stream);
 int hsrq_server_poll(hsrq_server_t server, hsrq_completion_t* out, int max, int* count, int wait_ms);
 int hsrq_server_clock(hsrq_server_t server, double* seconds);
 int hsrq_server_destroy(hsrq_server_t server);

@@ -133,7 +133,8 @@ def batch(H, wr, wi, B, nthreads=None):
     mu = np.zeros(m)
     info = np.zeros(m, dtype=np.int32)
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        # the host share of one GPU is 16 threads, whatever the machine has
+        nthreads = min(16, len(os.sched_getaffinity(0)))
     lib.hsrq_oracle_batch(n, _ptr(H), n, m, _ptr(wr), _ptr(wi), _ptr(B), n, _ptr(Y), n,
                           _ptr(E), _ptr(mu), _ptr(info), int(nthreads))
     return Y, E, mu, info
@@ -156,3 +157,45 @@ def hnorm_inf(H):
     lib = _load()
     H = _fortran(H)
     return float(lib.hsrq_oracle_hnorm_inf(H.shape[0], _ptr(H), H.shape[0]))
+
+
+def hsrq3in(H, wr, wi, S, ntries=None):
+    """Inverse iteration with restarts (Sec. 4.2, Algorithm 14).
+
+    Every shift is solved from the starting vector S[:, 0]; the shifts whose
+    result fails the convergence test are solved again from S[:, 1], those
+    that fail again from S[:, 2], up to S[:, ntries - 1].  A complex shift
+    starts from the real vector (imaginary part zero), as in Sec. 4.3.
+    Returns (Y, E, mu, info, tries) in the caller's column layout; tries[l] is
+    the 0-based try whose result is returned (the last one tried when none
+    converged, with info NOT_CONVERGED).
+    """
+    H = _fortran(H)
+    n = H.shape[0]
+    wr = np.asarray(wr, dtype=np.float64)
+    wi = np.asarray(wi, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    m = wr.shape[0]
+    ntries = S.shape[1] if ntries is None else ntries
+    cols, ncols = columns_of(wi)
+    Y = np.zeros((n, ncols))
+    E = np.zeros(m, dtype=np.int32)
+    mu = np.zeros(m)
+    info = np.zeros(m, dtype=np.int32)
+    tries = np.zeros(m, dtype=np.int32)
+    act = list(range(m))
+    for t in range(ntries):
+        if not act:
+            break
+        wr_a, wi_a = wr[act], wi[act]
+        ca, nca = columns_of(wi_a)
+        B = np.zeros((n, nca))
+        for k in range(len(act)):
+            B[:, ca[k]] = S[:, t]
+        Ya, Ea, mua, infoa = batch(H, wr_a, wi_a, B)
+        for k, l in enumerate(act):
+            w = 2 if wi[l] != 0.0 else 1
+            Y[:, cols[l]:cols[l] + w] = Ya[:, ca[k]:ca[k] + w]
+            E[l], mu[l], info[l], tries[l] = Ea[k], mua[k], infoa[k], t
+        act = [l for k, l in enumerate(act) if infoa[k] == NOT_CONVERGED]
+    return Y, E, mu, info, tries

@@ -26,6 +26,8 @@ EXPORTED = [
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
     "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune", "hsrq_fallback_count",
     "hsrq_server_create", "hsrq_server_submit", "hsrq_server_poll", "hsrq_server_clock", "hsrq_server_destroy",
+    "hsrq_hsrq3in_workspace_size", "hsrq_hsrq3in",
+    "hsrq_autotune_save", "hsrq_autotune_load",
 ]
 KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
@@ -33,7 +35,7 @@ KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 class HsrqOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("cols_per_block", ctypes.c_int), ("precision", ctypes.c_int),
                 ("residual", ctypes.c_int), ("graph", ctypes.c_int), ("rotations", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("share_min_far", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 class HsrqCompletion(ctypes.Structure):
@@ -75,10 +77,15 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), vp]
     lib.hsrq_fallback_count.argtypes = [vp, P(ctypes.c_int64)]
     lib.hsrq_server_create.argtypes = [P(vp), i, sz, P(HsrqOpts)]
-    lib.hsrq_server_submit.argtypes = [vp, P(HsrqProblem), ctypes.c_uint64]
+    lib.hsrq_server_submit.argtypes = [vp, P(HsrqProblem), ctypes.c_uint64, vp]
     lib.hsrq_server_poll.argtypes = [vp, P(HsrqCompletion), i, P(i), i]
     lib.hsrq_server_clock.argtypes = [vp, P(ctypes.c_double)]
     lib.hsrq_server_destroy.argtypes = [vp]
+    lib.hsrq_autotune_save.argtypes = [vp, ctypes.c_char_p]
+    lib.hsrq_autotune_load.argtypes = [vp, ctypes.c_char_p]
+    lib.hsrq_hsrq3in_workspace_size.argtypes = [vp, i, i, vp, P(HsrqOpts), P(sz)]
+    lib.hsrq_hsrq3in.argtypes = [vp, i, vp, i, i, vp, vp, vp, i, i, vp, i, vp, vp, vp, vp, vp, vp, sz,
+                                 P(HsrqOpts)]
     for f in EXPORTED:
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -96,13 +103,14 @@ def _check(st, what):
         raise RuntimeError(f"{what} failed with status {st}")
 
 
-def _opts(nb=0, precision=0, residual=False, graph=0, rotations=0):
+def _opts(nb=0, precision=0, residual=False, graph=0, rotations=0, share_min_far=0):
     o = HsrqOpts()
     o.nb = int(nb or 0)
     o.precision = int(precision)
     o.residual = 1 if residual else 0
     o.graph = int(graph)
     o.rotations = int(rotations)
+    o.share_min_far = int(share_min_far)
     return o
 
 
@@ -168,12 +176,14 @@ class Solver:
                                             ctypes.byref(o), ctypes.byref(out)), "hsrq_workspace_size")
         return out.value
 
-    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0):
+    def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0,
+               share_min_far=0):
         """Solve in place: X (device, n x ncols) holds the starting vectors and
         receives the unit vectors.  Returns (scale_exp, scale_mant, info,
         resid) device tensors of length m.  rotations=1 applies the
         off-diagonal rotations of a tile column as one product on the matrix
-        cores (default 0: one at a time, bit-identical to Alg. 1's order)."""
+        cores (default 0: one at a time, bit-identical to Alg. 1's order).
+        share_min_far: see hsrq_opts_t (0 = library default)."""
         torch = self.torch
         n = H.shape[0]
         wr = np.ascontiguousarray(wr, dtype=np.float64)
@@ -189,7 +199,7 @@ class Solver:
         mu = torch.empty(m, dtype=torch.float64, device=dev)
         info = torch.empty(m, dtype=torch.int32, device=dev)
         res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
-        o = _opts(nb, precision, residual, graph, rotations)
+        o = _opts(nb, precision, residual, graph, rotations, share_min_far)
         need = self.workspace_size(n, wi, nb, precision)
         wp, wb = self.workspace(need)
         self._stream(stream)
@@ -200,6 +210,45 @@ class Solver:
         _check(st, "hsrq_dhsrq3")
         self._keep = (Hc,)  # keep a temporary column-major copy alive until the stream runs
         return E, mu, info, res
+
+    def hsrq3in(self, H, wr, wi, S, nb=0, residual=False, stream=None, rotations=0, work_bytes=None):
+        """Inverse iteration with restarts (hsrq_hsrq3in): S (device, n x
+        ntries, column-major) holds the starting vectors of the successive
+        tries.  Returns (X, scale_exp, scale_mant, info, tries, resid) with X
+        column-major in the caller's column layout.  work_bytes bounds the
+        workspace (the library then solves the shifts in groups); default:
+        enough for one group."""
+        torch = self.torch
+        n = H.shape[0]
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        m = wr.shape[0]
+        Hc, ldh = colmajor(H)
+        Sc, lds = colmajor(S)
+        dev = H.device
+        X = torch.empty((ncols_of(wi), n), dtype=torch.float64, device=dev).t()
+        E = torch.empty(m, dtype=torch.int32, device=dev)
+        mu = torch.empty(m, dtype=torch.float64, device=dev)
+        info = torch.empty(m, dtype=torch.int32, device=dev)
+        tries = torch.empty(m, dtype=torch.int32, device=dev)
+        res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
+        o = _opts(nb, 0, residual, 0, rotations)
+        if work_bytes is None:
+            need = ctypes.c_size_t()
+            _check(self.lib.hsrq_hsrq3in_workspace_size(self.h, n, m, wi.ctypes.data_as(ctypes.c_void_p),
+                                                        ctypes.byref(o), ctypes.byref(need)),
+                   "hsrq_hsrq3in_workspace_size")
+            work_bytes = need.value
+        wp, wb = self.workspace(work_bytes)
+        self._stream(stream)
+        _check(self.lib.hsrq_hsrq3in(self.h, n, Hc.data_ptr(), ldh, m, wr.ctypes.data_as(ctypes.c_void_p),
+                                     wi.ctypes.data_as(ctypes.c_void_p), Sc.data_ptr(), lds, Sc.shape[1],
+                                     X.data_ptr(), n, E.data_ptr(), mu.data_ptr(), info.data_ptr(),
+                                     tries.data_ptr(), res.data_ptr() if res is not None else None,
+                                     ctypes.c_void_p(wp), min(wb, int(work_bytes)), ctypes.byref(o)),
+               "hsrq_hsrq3in")
+        self._keep = (Hc, Sc)
+        return X, E, mu, info, tries, res
 
     def solve(self, H, wr, wi, B, **kw):
         """Out-of-place: returns (Y, E, mu, info, resid) with Y column-major."""
@@ -233,14 +282,15 @@ class Solver:
             a.resid = res.data_ptr() if res is not None else None
         return arr, keep, outs
 
-    def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0):
+    def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0,
+                share_min_far=0):
         """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
         solved in place).  Returns a list of (E, mu, info, resid).  graph: 1
         replay as a HIP graph, -1 launch kernel by kernel, 0 library default
         (graph)."""
         count = len(problems)
         arr, keep, outs = self._problem_array(problems, residual)
-        o = _opts(nb, precision, residual, graph, rotations)
+        o = _opts(nb, precision, residual, graph, rotations, share_min_far)
         need = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
                "hsrq_workspace_size_batched")
@@ -268,6 +318,14 @@ class Solver:
         _check(self.lib.hsrq_autotune(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o),
                                       ctypes.byref(best), ms.ctypes.data_as(ctypes.c_void_p)), "hsrq_autotune")
         return best.value, {64: float(ms[0]), 128: float(ms[1])}
+
+    def autotune_save(self, path):
+        """Write the handle's tuned choices to a text file (hsrq_autotune_save)."""
+        _check(self.lib.hsrq_autotune_save(self.h, os.fsencode(path)), "hsrq_autotune_save")
+
+    def autotune_load(self, path):
+        """Merge a file written by autotune_save into the handle."""
+        _check(self.lib.hsrq_autotune_load(self.h, os.fsencode(path)), "hsrq_autotune_load")
 
     def fallback_count(self):
         """Shifts re-solved in FP64 by the last mixed-precision call."""
@@ -334,9 +392,11 @@ class Server:
         self.h = h
         self._pending = {}
 
-    def submit(self, H, wr, wi, X, tag):
+    def submit(self, H, wr, wi, X, tag, stream=None):
         """Queue one request; returns (E, mu, info, resid) device tensors.
-        Raises on an invalid request; returns None if it can never fit."""
+        Raises on an invalid request; returns None if it can never fit.  The
+        server's kernels for the request wait for the work enqueued so far on
+        `stream` (default: torch's current stream), which produced H and X."""
         torch = self.torch
         Hc, ldh = colmajor(H)
         wr = np.ascontiguousarray(wr, dtype=np.float64)
@@ -353,7 +413,8 @@ class Server:
         a.X, a.ldx = X.data_ptr(), (X.stride(1) if X.shape[1] > 1 else Hc.shape[0])
         a.scale_exp, a.scale_mant, a.info = E.data_ptr(), mu.data_ptr(), info.data_ptr()
         a.resid = res.data_ptr() if res is not None else None
-        st = self.lib.hsrq_server_submit(self.h, ctypes.byref(a), int(tag))
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        st = self.lib.hsrq_server_submit(self.h, ctypes.byref(a), int(tag), ctypes.c_void_p(s.cuda_stream))
         if st == -1005:
             return None
         _check(st, "hsrq_server_submit")

@@ -35,8 +35,14 @@ struct ProbDesc {
   double *V, *X, *Y, *C, *S, *PHI, *Z0, *Z1, *W0, *W1;
   double *BMAX, *VMAX, *BSSQ, *BCMX, *TN, *FIN;
   int32_t *AX, *AMAX;
-  // zero-initialised per call: row sums, ||H||_F^2, flags, residual sums
-  double *RSUM, *HF, *RNUM;
+  // partial sums written once per call and reduced in a fixed order, so that
+  // every norm is the same on every run: row sums of |h| per (row, tile
+  // column) RPART[jt * n + row], sums of h^2 per tile pair HFP[i * N + jt],
+  // residual sums of squares per (64-row block, column) RNUMP[rb * ld + col]
+  double *RPART, *HFP, *RNUMP;
+  // zero-initialised per call: ||H||_F^2 (written by the reduction), flags,
+  // ||H||_inf (a maximum of non-negative doubles, taken on their bit patterns)
+  double* HF;
   int32_t* FLAG;
   double* HN;
   // column metadata (device)

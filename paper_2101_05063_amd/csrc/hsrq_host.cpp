@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -94,6 +95,7 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.ld = std::max(8, (q.ncols + 7) & ~7);
     q.nblk = (q.ncols + kCB - 1) / kCB;
     if (q.ncols > 0) Tmax = std::max(Tmax, q.N);
+    P.nmax = std::max(P.nmax, q.n);
   }
   // tasks: step t = 0 chains the last tile; step t >= 1 works on tile column
   // jt = N - t (critical tasks first, then far tasks)
@@ -156,16 +158,14 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.o_meta_i = off; off = align_up(off + sizeof(int32_t) * 4 * q.ld);
   }
   P.head_bytes = off;
-  // zero-initialised accumulators of every problem, contiguous for one fill:
-  // row sums (n), ||H||_F^2 (1), flags (1 slot), ||H||_inf (1), residual sums (ld)
+  // zero-initialised scalars of every problem, contiguous for one fill:
+  // ||H||_F^2 (1), flags (1 slot), ||H||_inf (1)
   P.o_zero_all = off;
   for (auto& q : P.pp) {
     q.o_zero = off;
-    q.o_RSUM = off; off += sizeof(double) * q.n;
     q.o_HF = off; off += sizeof(double);
     q.o_FLAG = off; off += sizeof(double);
     q.o_HN = off; off += sizeof(double);
-    q.o_RNUM = off; off += sizeof(double) * q.ld;
   }
   P.zero_count = (off - P.o_zero_all) / sizeof(double);
   off = align_up(off);
@@ -188,6 +188,9 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.o_AX = off; off = align_up(off + sizeof(int32_t) * (size_t)q.N * q.ld);
     q.o_AMAX = off; off = align_up(off + sizeof(int32_t) * q.ld);
     q.o_TN = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.N);
+    q.o_RPART = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.n);
+    q.o_HFP = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.N);
+    q.o_RNUMP = off; off = align_up(off + sizeof(double) * (size_t)((q.n + 63) / 64) * q.ld);
     const size_t nch = (q.n + kChunk - 1) / kChunk;
     q.o_FIN = off; off = align_up(off + sizeof(double) * (nch * 8 + 1) * q.ld);
   }
@@ -227,11 +230,12 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
     d.FIN = at<double>(work, q.o_FIN);
     d.AX = at<int32_t>(work, q.o_AX);
     d.AMAX = at<int32_t>(work, q.o_AMAX);
-    d.RSUM = at<double>(work, q.o_RSUM);
+    d.RPART = at<double>(work, q.o_RPART);
+    d.HFP = at<double>(work, q.o_HFP);
+    d.RNUMP = at<double>(work, q.o_RNUMP);
     d.HF = at<double>(work, q.o_HF);
     d.FLAG = at<int32_t>(work, q.o_FLAG);
     d.HN = at<double>(work, q.o_HN);
-    d.RNUM = at<double>(work, q.o_RNUM);
     d.lam_re = at<double>(work, q.o_meta_d);
     d.lam_im = at<double>(work, q.o_meta_d) + q.ld;
     d.coltype = at<int32_t>(work, q.o_meta_i);
@@ -291,7 +295,9 @@ struct hsrq_handle_s {
   bool staging_pending = false;
   // second stream for the far-tile kernels, and fork/join events
   hipStream_t aux = nullptr;
-  std::vector<hipEvent_t> sync_ev;
+  // fork, critical step done, far step done: each wait is enqueued before the
+  // event is recorded again, and a wait refers to the record preceding it
+  hipEvent_t sync_ev[3] = {nullptr, nullptr, nullptr};
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -366,6 +372,7 @@ bool opts_ok(const hsrq_opts_t* o) {
   if (o->residual != 0 && o->residual != 1) return false;
   if (o->graph < -1 || o->graph > 1) return false;
   if (o->rotations != 0 && o->rotations != 1) return false;
+  if (o->share_min_far < -1) return false;
   return true;
 }
 
@@ -381,6 +388,10 @@ int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsr
   return heuristic_nb(count, probs);
 }
 
+// pinned staging buffer created with the handle (grown by later calls that
+// need more; the no-allocation entry point only uses what is there)
+constexpr size_t kStagingBytes = size_t(2) << 20;
+
 int ensure_staging(hsrq_handle_t h, size_t bytes) {
   if (h->staging_pending) {
     if (hipEventSynchronize(h->staging_ev) != hipSuccess) return HSRQ_ERR_HIP;
@@ -390,7 +401,7 @@ int ensure_staging(hsrq_handle_t h, size_t bytes) {
   if (h->staging) hipHostFree(h->staging);
   h->staging = nullptr;
   h->staging_bytes = 0;
-  size_t want = std::max<size_t>(bytes, 1 << 20);
+  size_t want = std::max<size_t>(bytes, kStagingBytes);
   if (hipHostMalloc(&h->staging, want, hipHostMallocDefault) != hipSuccess) {
     h->staging = nullptr;
     return HSRQ_ERR_ALLOC;
@@ -432,15 +443,15 @@ struct ProfScope {
   }
 };
 
-int ensure_sync_events(hsrq_handle_t h, int T) {
-  if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
-  while ((int)h->sync_ev.size() < 2 * T + 2) {
-    hipEvent_t e;
+// the handle's second stream and its three fork/join events, created with
+// the handle (nothing is created inside a solve)
+int create_sync(hsrq_handle_t h) {
+  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return HSRQ_ERR_HIP;
+  for (hipEvent_t& e : h->sync_ev) {
     // ordering between the handle's two streams on one device: a release at
     // device scope is enough, and it spares the system-scope cache writeback
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
       return HSRQ_ERR_HIP;
-    h->sync_ev.push_back(e);
   }
   return HSRQ_OK;
 }
@@ -462,40 +473,36 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
   {
     ProfScope ps(h, HSRQ_K_PREP, s);
     launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
-    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, s);
+    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, P.nmax, s);
   }
   { ProfScope ps(h, HSRQ_K_INIT, s); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
   // steps: critical tasks on s, far tasks on the second stream; step t of
   // either kind waits for both kinds of step t-1
   const int T = (int)P.coff.size();
   hipStream_t a = h->aux;
-  hipEvent_t* ev = h->sync_ev.data();
-  // ev[2t]: critical step t done; ev[2t+1]: far step t done; ev[2T]: fork
-  hipEventRecord(ev[2 * T], s);
-  hipStreamWaitEvent(a, ev[2 * T], 0);
+  hipEvent_t ev_fork = h->sync_ev[0], ev_crit = h->sync_ev[1], ev_far = h->sync_ev[2];
+  hipEventRecord(ev_fork, s);
+  hipStreamWaitEvent(a, ev_fork, 0);
   for (int t = 0; t < T; ++t) {
-    if (t > 0) {
-      hipStreamWaitEvent(s, ev[2 * (t - 1) + 1], 0);
-      hipStreamWaitEvent(a, ev[2 * (t - 1)], 0);
+    if (t > 0) {  // the records of step t-1
+      hipStreamWaitEvent(s, ev_far, 0);
+      hipStreamWaitEvent(a, ev_crit, 0);
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s, true);
-      launch_crit(P.nb, P.prec, P.l3rot, P.fcnt[t] >= kShareFar, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
+      launch_crit(P.nb, P.prec, P.l3rot, P.fcnt[t] >= P.share, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
     }
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
       ProfScope ps(h, HSRQ_K_FAR, a, true);
       launch_far(P.nb, P.prec, P.l3rot, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
     }
-    hipEventRecord(ev[2 * t], s);
-    hipEventRecord(ev[2 * t + 1], a);
+    hipEventRecord(ev_crit, s);
+    hipEventRecord(ev_far, a);
   }
-  // join: the second stream's last step (or the fork, with no steps)
-  hipStreamWaitEvent(s, T > 0 ? ev[2 * (T - 1) + 1] : ev[2 * T], 0);
-  if (T == 0) {
-    hipEventRecord(ev[2 * T + 1], a);
-    hipStreamWaitEvent(s, ev[2 * T + 1], 0);
-  }
+  // join: the second stream's last step (with no steps, its wait for the fork)
+  if (T == 0) hipEventRecord(ev_far, a);
+  hipStreamWaitEvent(s, ev_far, 0);
   {
     ProfScope ps(h, HSRQ_K_FINAL, s);
     launch_final(dd, at<int2>(work, P.o_bcols), (int)P.blk_cols.size(), at<int4>(work, P.o_bfin),
@@ -522,6 +529,7 @@ uint64_t plan_signature(const Plan& P, int count, void* work, bool want_res) {
   Sig g;
   g.add((uint64_t)P.nb);
   g.add((uint64_t)(P.prec * 2 + P.l3rot));
+  g.add((uint64_t)(uint32_t)P.share);
   g.add((uint64_t)count);
   g.add((uint64_t)reinterpret_cast<uintptr_t>(work));
   g.add((uint64_t)want_res);
@@ -624,6 +632,28 @@ bool use_graph(hsrq_handle_t h, const hsrq_opts_t* o, bool batched) {
   return g > 0 || (g == 0 && batched);
 }
 
+// The handle's pinned buffer of copy lists (read in place by the copy
+// kernel), at least `need` bytes, once the kernels reading it have finished.
+int ensure_lists(hsrq_handle_t h, size_t need) {
+  if (h->lists_pending) {
+    if (hipEventSynchronize(h->lists_ev) != hipSuccess) return HSRQ_ERR_HIP;
+    h->lists_pending = false;
+  }
+  if (!h->lists_ev && hipEventCreateWithFlags(&h->lists_ev, hipEventDisableTiming) != hipSuccess)
+    return HSRQ_ERR_HIP;
+  if (h->lists_bytes < need) {
+    if (h->lists) hipHostFree(h->lists);
+    h->lists = nullptr;
+    h->lists_bytes = 0;
+    if (hipHostMalloc(&h->lists, need, hipHostMallocDefault) != hipSuccess) {
+      h->lists = nullptr;
+      return HSRQ_ERR_ALLOC;
+    }
+    h->lists_bytes = need;
+  }
+  return HSRQ_OK;
+}
+
 // Mixed precision (opts->precision == 1), in three phases:
 //   1. the whole solve with FP32 tile-update products (every rotation, scale
 //      factor, small solve and the normalisation stay FP64), and the FP64
@@ -670,12 +700,12 @@ int run_mixed(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* wor
   Plan P;
   build_plan(P, count, probs, nb);
   P.prec = 1;
+  P.share = share_min(o);
   const MixedLayout L = mixed_layout(count, probs, P.total_bytes);
   if (!work || work_bytes < L.total || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
     return HSRQ_ERR_WORKSPACE;
   hipStream_t s = h->stream;
-  int st = ensure_sync_events(h, (int)P.coff.size());
-  if (st) return st;
+  int st = HSRQ_OK;
   // phase 1: residuals go to the caller's array if given, else to ours
   std::vector<hsrq_problem_t> q1(probs, probs + count);
   for (int p = 0; p < count; ++p)
@@ -793,22 +823,7 @@ int run_mixed(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* wor
   // both lists in one pinned buffer that the copy kernel reads in place
   {
     const size_t need = sizeof(CopyEnt) * (gather.size() + scatter.size());
-    if (h->lists_pending) {
-      if (hipEventSynchronize(h->lists_ev) != hipSuccess) return HSRQ_ERR_HIP;
-      h->lists_pending = false;
-    }
-    if (!h->lists_ev && hipEventCreateWithFlags(&h->lists_ev, hipEventDisableTiming) != hipSuccess)
-      return HSRQ_ERR_HIP;
-    if (h->lists_bytes < need) {
-      if (h->lists) hipHostFree(h->lists);
-      h->lists = nullptr;
-      h->lists_bytes = 0;
-      if (hipHostMalloc(&h->lists, need, hipHostMallocDefault) != hipSuccess) {
-        h->lists = nullptr;
-        return HSRQ_ERR_ALLOC;
-      }
-      h->lists_bytes = need;
-    }
+    if ((st = ensure_lists(h, need))) return st;
     std::memcpy(h->lists, gather.data(), sizeof(CopyEnt) * gather.size());
     std::memcpy(static_cast<CopyEnt*>(h->lists) + gather.size(), scatter.data(), sizeof(CopyEnt) * scatter.size());
   }
@@ -822,9 +837,9 @@ int run_mixed(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* wor
   build_plan(P2, (int)q2.size(), q2.data(), nb);
   P2.prec = 0;
   P2.l3rot = o->rotations;
+  P2.share = share_min(o);
   void* w2 = at<char>(work, L.o_pass2);
   if (P2.total_bytes > P.total_bytes) return HSRQ_ERR_WORKSPACE;
-  if ((st = ensure_sync_events(h, (int)P2.coff.size()))) return st;
   if ((st = ensure_staging(h, P2.head_bytes))) return st;
   hsrq_opts_t o2 = *o;
   o2.precision = 0;
@@ -845,11 +860,11 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
   Plan P;
   build_plan(P, count, probs, choose_nb(h, count, probs, o));
   P.l3rot = o ? o->rotations : 0;
+  P.share = share_min(o);
   if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
     return HSRQ_ERR_WORKSPACE;
   const bool want_res = wants_residual(o, count, probs);
-  int st = ensure_sync_events(h, (int)P.coff.size());
-  if (st) return st;
+  int st = HSRQ_OK;
   hipStream_t s = h->stream;
   if (use_graph(h, o, batched)) return run_graph(h, P, count, probs, work, o, want_res, s);
   st = ensure_staging(h, P.head_bytes);
@@ -859,6 +874,16 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
   h->staging_pending = true;
   return st;
 }
+
+}  // namespace
+
+namespace hsrq {
+
+bool opts_valid(const hsrq_opts_t* o) { return opts_ok(o); }
+
+}  // namespace hsrq
+
+namespace {
 
 // bytes of workspace for any tile size the library may pick (nb = 0)
 size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
@@ -874,9 +899,198 @@ size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const
   return b;
 }
 
+// ---------------------------------------------------------------------------
+// Inverse iteration with restarts (Sec. 4.2, Algorithm 14) over groups of
+// shifts sized by the workspace (Algorithm 15).
+// ---------------------------------------------------------------------------
+// The driver's workspace for a group of `cols` columns of order n: the
+// solve's workspace (the plan's sizes depend on n and the column count only,
+// so a problem of `cols` real shifts stands for any group of that many
+// columns), the compacted columns of a restart, its per-shift outputs, and
+// one column of zeros (the imaginary part of a complex shift's start).
+struct InLayout {
+  size_t solve = 0, o_cols = 0, o_scal = 0, o_zero = 0, total = 0;
+};
+
+InLayout in_layout(hsrq_handle_t h, int n, int cols, const hsrq_opts_t* o) {
+  std::vector<double> z(std::max(cols, 1), 0.0);
+  hsrq_problem_t p{};
+  p.n = n;
+  p.m = cols;
+  p.wr = z.data();
+  p.wi = z.data();
+  InLayout L;
+  L.solve = align_up(plan_bytes(h, 1, &p, o));
+  size_t off = L.solve;
+  L.o_cols = off;
+  off = align_up(off + sizeof(double) * (size_t)n * cols);
+  L.o_scal = off;  // resid, mu (doubles), then E, info (int32) of the restart's shifts
+  off = align_up(off + (sizeof(double) * 2 + sizeof(int32_t) * 2) * (size_t)std::max(cols, 1) + 64);
+  L.o_zero = off;
+  off = align_up(off + sizeof(double) * (size_t)n);
+  L.total = off;
+  return L;
+}
+
+int run_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh, int m, const double* wr, const double* wi,
+                const double* S, int lds, int ntries, double* X, int ldx, int32_t* E, double* mu, int32_t* info,
+                int32_t* tries, double* resid, void* work, size_t work_bytes, const hsrq_opts_t* o) {
+  if (!work || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1))) return HSRQ_ERR_WORKSPACE;
+  hipStream_t s = h->stream;
+  std::vector<int> width(m), col(m);  // columns of each shift, first caller column
+  int total = 0;
+  bool any_cplx = false;
+  for (int l = 0; l < m; ++l) {
+    width[l] = wi[l] != 0.0 ? 2 : 1;
+    any_cplx |= width[l] == 2;
+    col[l] = total;
+    total += width[l];
+  }
+  // group size (Algorithm 15): the most columns whose workspace fits
+  int lo = 0, hi = total;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (in_layout(h, n, mid, o).total <= work_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int G = lo;
+  if (G < 1 || (any_cplx && G < 2)) return HSRQ_ERR_WORKSPACE;
+  const InLayout L = in_layout(h, n, G, o);
+  double* zero = at<double>(work, L.o_zero);
+  launch_fill(zero, n, 0.0, s);
+  const bool want_res = resid && o && o->residual;
+  int st = HSRQ_OK;
+  for (int l0 = 0; l0 < m;) {
+    int l1 = l0, cols = 0;
+    while (l1 < m && cols + width[l1] <= G) cols += width[l1++];
+    std::vector<int> act;  // shifts of the group not yet converged, in input order
+    for (int l = l0; l < l1; ++l) act.push_back(l);
+    for (int t = 0; t < ntries && !act.empty(); ++t) {
+      const bool first = t == 0;
+      const int ma = (int)act.size();
+      std::vector<double> wr2(ma), wi2(ma);
+      for (int k = 0; k < ma; ++k) {
+        wr2[k] = wr[act[k]];
+        wi2[k] = wi[act[k]];
+      }
+      // the first try solves in the caller's arrays (the group's columns are
+      // contiguous there); a restart solves the remaining shifts compacted in
+      // the workspace and copies its outputs back over the caller's
+      hsrq_problem_t p{};
+      p.n = n;
+      p.H = H;
+      p.ldh = ldh;
+      p.m = ma;
+      p.wr = wr2.data();
+      p.wi = wi2.data();
+      char* sc = at<char>(work, L.o_scal);
+      if (first) {
+        p.X = X + (size_t)col[l0] * ldx;
+        p.ldx = ldx;
+        p.scale_exp = E + l0;
+        p.scale_mant = mu + l0;
+        p.info = info + l0;
+        p.resid = want_res ? resid + l0 : nullptr;
+      } else {
+        p.X = at<double>(work, L.o_cols);
+        p.ldx = n;
+        p.resid = want_res ? reinterpret_cast<double*>(sc) : nullptr;
+        p.scale_mant = reinterpret_cast<double*>(sc) + G;
+        p.scale_exp = reinterpret_cast<int32_t*>(reinterpret_cast<double*>(sc) + 2 * G);
+        p.info = p.scale_exp + G;
+      }
+      // copy lists (pinned, read in place): the starting vector S(:, t) into
+      // every column of the problem (zeros into the imaginary columns), then,
+      // after the solve, a restart's outputs to the caller and the try index
+      std::vector<CopyEnt> pre, post;
+      for (int k = 0, c2 = 0; k < ma; ++k) {
+        const int l = act[k];
+        for (int q = 0; q < width[l]; ++q) {
+          double* dst = p.X + (size_t)(c2 + q) * p.ldx;
+          pre.push_back(CopyEnt{q == 0 ? S + (size_t)t * lds : zero, dst, (long long)sizeof(double) * n});
+          if (!first) post.push_back(CopyEnt{dst, X + (size_t)(col[l] + q) * ldx, (long long)sizeof(double) * n});
+        }
+        c2 += width[l];
+        if (!first) {
+          post.push_back(CopyEnt{p.scale_exp + k, E + l, (long long)sizeof(int32_t)});
+          post.push_back(CopyEnt{p.scale_mant + k, mu + l, (long long)sizeof(double)});
+          post.push_back(CopyEnt{p.info + k, info + l, (long long)sizeof(int32_t)});
+          if (want_res) post.push_back(CopyEnt{p.resid + k, resid + l, (long long)sizeof(double)});
+        }
+      }
+      const size_t ents = pre.size() + post.size() + (tries ? ma : 0);
+      if ((st = ensure_lists(h, sizeof(CopyEnt) * ents + sizeof(int32_t) * ma))) return st;
+      CopyEnt* le = static_cast<CopyEnt*>(h->lists);
+      int32_t* tv = reinterpret_cast<int32_t*>(le + ents);
+      std::memcpy(le, pre.data(), sizeof(CopyEnt) * pre.size());
+      std::memcpy(le + pre.size(), post.data(), sizeof(CopyEnt) * post.size());
+      for (int k = 0; k < ma; ++k) {
+        tv[k] = t;
+        if (tries) le[pre.size() + post.size() + k] = CopyEnt{tv + k, tries + act[k], (long long)sizeof(int32_t)};
+      }
+      launch_copy(le, (int)pre.size(), s);
+      if ((st = run(h, 1, &p, work, L.solve, o, false))) return st;
+      launch_copy(le + pre.size(), (int)(ents - pre.size()), s);
+      if (hipEventRecord(h->lists_ev, s) != hipSuccess) return HSRQ_ERR_HIP;
+      h->lists_pending = true;
+      // the flags decide the next try
+      std::vector<int32_t> fl(ma);
+      if (hipMemcpyAsync(fl.data(), p.info, sizeof(int32_t) * ma, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return HSRQ_ERR_HIP;
+      std::vector<int> next;
+      for (int k = 0; k < ma; ++k)
+        if (fl[k] == 1) next.push_back(act[k]);
+      act.swap(next);
+    }
+    l0 = l1;
+  }
+  return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
+
+int hsrq_hsrq3in_workspace_size(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_opts_t* opts,
+                                size_t* bytes) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (m < 0) return -3;
+  if (m > 0 && !wi) return -4;
+  if (!opts_ok(opts) || (opts && opts->precision != 0)) return -5;
+  if (!bytes) return -6;
+  *bytes = in_layout(h, n, m > 0 ? count_cols(m, wi) : 1, opts).total;
+  return HSRQ_OK;
+}
+
+int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh, int m, const double* wr, const double* wi,
+                 const double* S, int lds, int ntries, double* X, int ldx, int32_t* scale_exp,
+                 double* scale_mant, int32_t* info, int32_t* tries, double* resid, void* work, size_t work_bytes,
+                 const hsrq_opts_t* opts) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!H) return -3;
+  if (ldh < n) return -4;
+  if (m < 0) return -5;
+  if (m > 0 && !wr) return -6;
+  if (m > 0 && !wi) return -7;
+  if (m > 0 && !S) return -8;
+  if (lds < n) return -9;
+  if (ntries < 1) return -10;
+  if (m > 0 && !X) return -11;
+  if (ldx < n) return -12;
+  if (m > 0 && !scale_exp) return -13;
+  if (m > 0 && !scale_mant) return -14;
+  if (m > 0 && !info) return -15;
+  if (!work) return -18;
+  if (!opts_ok(opts) || (opts && opts->precision != 0)) return -20;
+  if (m == 0) return HSRQ_OK;
+  return run_hsrq3in(h, n, H, ldh, m, wr, wi, S, lds, ntries, X, ldx, scale_exp, scale_mant, info, tries, resid,
+                     work, work_bytes, opts);
+}
 
 int hsrq_create(hsrq_handle_t* out, int device) {
   if (!out) return -1;
@@ -886,9 +1100,15 @@ int hsrq_create(hsrq_handle_t* out, int device) {
   hsrq_handle_t h = new (std::nothrow) hsrq_handle_s();
   if (!h) return HSRQ_ERR_ALLOC;
   h->device = device;
-  if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) {
-    delete h;
-    return HSRQ_ERR_HIP;
+  // everything a solve needs on the host side is created here: the staging
+  // buffer, the second stream and its events
+  int st = HSRQ_OK;
+  if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) st = HSRQ_ERR_HIP;
+  if (st == HSRQ_OK) st = create_sync(h);
+  if (st == HSRQ_OK) st = ensure_staging(h, kStagingBytes);
+  if (st) {
+    hsrq_destroy(h);
+    return st;
   }
   *out = h;
   return HSRQ_OK;
@@ -944,7 +1164,8 @@ int hsrq_destroy(hsrq_handle_t h) {
   if (h->lists_ev) hipEventDestroy(h->lists_ev);
   if (h->cap) hipStreamDestroy(h->cap);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
-  for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
+  for (hipEvent_t e : h->sync_ev)
+    if (e) hipEventDestroy(e);
   if (h->aux) {
     hipStreamSynchronize(h->aux);
     hipStreamDestroy(h->aux);
@@ -1029,8 +1250,8 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
     build_plan(P, count, problems, nb);
     P.prec = o.precision == 1 ? 1 : 0;
     P.l3rot = o.rotations;
+    P.share = share_min(&o);
     if (work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1))) continue;
-    if ((st = ensure_sync_events(h, (int)P.coff.size()))) break;
     float t_best = 0.f;
     for (int rep = 0; rep < 3 && st == HSRQ_OK; ++rep) {  // first run warms up
       if ((st = ensure_staging(h, P.head_bytes))) break;
@@ -1086,6 +1307,52 @@ int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_
   if (col_of) {
     for (int c = 0; c < q.ncols; ++c)
       if (q.lay.coltype[c] != CT_CIM) col_of[q.lay.colshift[c]] = c;
+  }
+  return HSRQ_OK;
+}
+
+// Tuner cache: one line per problem-set signature, "<signature hex> <nb>",
+// after a header line; entries loaded are merged into the handle's (a loaded
+// entry replaces one with the same signature).
+int hsrq_autotune_save(hsrq_handle_t h, const char* path) {
+  if (!h || !path) return HSRQ_ERR_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return HSRQ_ERR_ARG;
+  bool ok = std::fprintf(f, "hsrq-tuner 1\n") > 0;
+  for (auto& e : h->tuned) ok = ok && std::fprintf(f, "%016llx %d\n", (unsigned long long)e.first, e.second) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? HSRQ_OK : HSRQ_ERR_ARG;
+}
+
+int hsrq_autotune_load(hsrq_handle_t h, const char* path) {
+  if (!h || !path) return HSRQ_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return HSRQ_ERR_ARG;
+  char head[32] = {0};
+  int st = HSRQ_OK;
+  if (!std::fgets(head, sizeof head, f) || std::strncmp(head, "hsrq-tuner 1", 12) != 0) st = HSRQ_ERR_ARG;
+  std::vector<std::pair<uint64_t, int>> got;
+  unsigned long long key = 0;
+  int nb = 0;
+  while (st == HSRQ_OK) {
+    const int r = std::fscanf(f, "%llx %d", &key, &nb);
+    if (r == EOF) break;
+    if (r != 2 || (nb != 64 && nb != 128)) {
+      st = HSRQ_ERR_ARG;
+      break;
+    }
+    got.emplace_back((uint64_t)key, nb);
+  }
+  std::fclose(f);
+  if (st) return st;  // nothing merged from a malformed file
+  for (auto& g : got) {
+    bool found = false;
+    for (auto& e : h->tuned)
+      if (e.first == g.first) {
+        e.second = g.second;
+        found = true;
+      }
+    if (!found) h->tuned.push_back(g);
   }
   return HSRQ_OK;
 }

@@ -13,14 +13,20 @@
 
 namespace hsrq {
 
-void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, hipStream_t st);
+// nmax: the largest order among the nprob problems
+void launch_prep(const ProbDesc* d, const int4* blk, int nblk, int nprob, int nmax, hipStream_t st);
 void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 // allow the critical kernels their dynamic shared memory on the current
 // device (0, or -1 on a HIP error); called once per handle and server
 int crit_smem_init();
 // share: the critical kernel variant that leaves room on its CU for one
-// far-tile block (used for steps with at least kShareFar far-tile blocks)
+// far-tile block (used for steps with at least share_min far-tile blocks;
+// kShareFar by default, opts.share_min_far otherwise)
 constexpr int kShareFar = 512;
+inline int share_min(const hsrq_opts_t* o) {
+  if (!o || o->share_min_far == 0) return kShareFar;
+  return o->share_min_far < 0 ? 0x7fffffff : o->share_min_far;
+}
 void launch_crit(int nb, int prec, int l3rot, bool share, const ProbDesc* d, const Task* tasks, int ntasks,
                  hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
@@ -51,13 +57,14 @@ struct ProbPlan {
   // byte offsets inside the workspace
   size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
   size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_W0, o_W1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
-  size_t o_zero, o_RSUM, o_HF, o_FLAG, o_RNUM, o_HN;
+  size_t o_zero, o_HF, o_FLAG, o_HN, o_RPART, o_HFP, o_RNUMP;
 };
 
 struct Plan {
   int nb = 64;
   int prec = 0;    // 1: FP32 tile-update products
   int l3rot = 0;   // 1: off-diagonal rotations folded and applied on MFMA (opts.rotations)
+  int share = kShareFar;  // far-tile blocks from which a step uses the CU-sharing critical kernel
   std::vector<ProbPlan> pp;
   std::vector<Task> tasks;
   std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
@@ -66,6 +73,7 @@ struct Plan {
   size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin;
   size_t head_bytes, total_bytes;
   size_t o_zero_all = 0, zero_count = 0;  // doubles
+  int nmax = 0;                           // largest order
 };
 
 // Carve the workspace and build every host-side table.
@@ -81,6 +89,9 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
                   char* hb);
 // 0, or -k for an invalid k-th argument of the single-problem call
 int check_problem(const hsrq_problem_t& p);
+// options outside their documented values
+bool opts_valid(const hsrq_opts_t* o);
+
 
 template <class T>
 T* at(void* base, size_t off) {

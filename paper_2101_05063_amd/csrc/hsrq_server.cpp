@@ -100,6 +100,7 @@ struct Req {
   int t = 0;
   ReqState state = RQ_QUEUED;
   hipEvent_t ev = nullptr;  // completion of the last enqueued phase
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
   int status = HSRQ_OK;
   int fallback = 0;
   // mixed precision
@@ -107,6 +108,9 @@ struct Req {
   std::vector<int> fail;       // failing shifts (parent)
   Req* parent = nullptr;       // set on a fallback child
   Req* child = nullptr;
+  ~Req() {
+    if (ready) hipEventDestroy(ready);
+  }
   std::vector<int> child_cols;  // parent column of each child column
   std::vector<CopyEnt> scatter;
   void* lists = nullptr;
@@ -190,10 +194,12 @@ int admit(hsrq_server_s* S, Req* r) {
   std::memcpy(&r->desc, static_cast<char*>(r->head) + r->plan.o_desc, sizeof(ProbDesc));
   const Plan& P = r->plan;
   hipStream_t s = S->s;
+  // the caller's H and X are complete once its stream reaches the submission
+  if (r->ready && hipStreamWaitEvent(s, r->ready, 0) != hipSuccess) return HSRQ_ERR_HIP;
   if (hipMemcpyAsync(r->work, r->head, P.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
   const ProbDesc* dd = at<ProbDesc>(r->work, P.o_desc);
   launch_fill(at<double>(r->work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
-  launch_prep(dd, at<int4>(r->work, P.o_bprep), (int)P.blk_prep.size(), 1, s);
+  launch_prep(dd, at<int4>(r->work, P.o_bprep), (int)P.blk_prep.size(), 1, P.nmax, s);
   launch_init(dd, at<int4>(r->work, P.o_binit), (int)P.blk_init.size(), s);
   if (r->prec == 1 && r->prob.m > 0) {  // keep the starting vectors for the fallback
     const size_t cols = (size_t)count_cols(r->prob.m, r->prob.wi);
@@ -283,7 +289,7 @@ int tick(hsrq_server_s* S) {
   const ProbDesc* dd = reinterpret_cast<const ProbDesc*>(db);
   for (int pr = 0; pr < 2; ++pr) {
     if (!crit[pr].empty())
-      launch_crit(S->nb, pr, S->opts.rotations, (int)far[pr].size() >= kShareFar, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
+      launch_crit(S->nb, pr, S->opts.rotations, (int)far[pr].size() >= share_min(&S->opts), dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
       launch_far(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
   }
@@ -388,7 +394,7 @@ int check_request(hsrq_server_s* S, Req* r) {
   if (hipMemcpyAsync(w, c->head, P2.head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return HSRQ_ERR_HIP;
   const ProbDesc* dd = at<ProbDesc>(w, P2.o_desc);
   launch_fill(at<double>(w, P2.o_zero_all), (long long)P2.zero_count, 0.0, s);
-  launch_prep(dd, at<int4>(w, P2.o_bprep), (int)P2.blk_prep.size(), 1, s);
+  launch_prep(dd, at<int4>(w, P2.o_bprep), (int)P2.blk_prep.size(), 1, P2.nmax, s);
   launch_init(dd, at<int4>(w, P2.o_binit), (int)P2.blk_init.size(), s);
   c->work_cap = wc;
   c->t = 0;
@@ -603,7 +609,7 @@ int hsrq_server_create(hsrq_server_t* out, int device, size_t hbm_budget_bytes, 
   return HSRQ_OK;
 }
 
-int hsrq_server_submit(hsrq_server_t S, const hsrq_problem_t* problem, uint64_t tag) {
+int hsrq_server_submit(hsrq_server_t S, const hsrq_problem_t* problem, uint64_t tag, void* stream) {
   if (!S || !problem) return HSRQ_ERR_ARG;
   const int chk = check_problem(*problem);
   if (chk || problem->m < 1) return HSRQ_ERR_ARG;
@@ -622,6 +628,17 @@ int hsrq_server_submit(hsrq_server_t S, const hsrq_problem_t* problem, uint64_t 
   if (r->prec == 1) r->charge += r->charge / 2;  // room for a fallback child
   if (r->charge > S->budget) return HSRQ_ERR_BUSY;
   if (tick_bytes_estimate(r.get(), S->nb) > (int)(kTickBytes / kRing) / 2) return HSRQ_ERR_BUSY;
+  {
+    // order the request after the work the caller has enqueued on its
+    // stream so far (NULL is the null stream, torch's default stream; the
+    // event is created on the server's device)
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(S->device) != hipSuccess) return HSRQ_ERR_HIP;
+    hipError_t e = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->ready, static_cast<hipStream_t>(stream));
+    hipSetDevice(cur);
+    if (e != hipSuccess) return HSRQ_ERR_HIP;
+  }
   {
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stop || S->init_status) return HSRQ_ERR_ARG;

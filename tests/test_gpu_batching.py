@@ -146,3 +146,42 @@ def test_c4_batched_sampled(solver):
         n = pr["H"].shape[0]
         compare(*args, dir_tol=1e-10, mu_tol=100 * n * 2.0 ** -52, sel=good)
         compare(*args, dir_tol=1e-6, mu_tol=1e-8, sel=rest)
+
+
+def test_tuner_cache_round_trip(solver, tmp_path):
+    """The tuner's choice for a problem set, saved to a file and loaded into a
+    new handle, is what that handle's planner uses (nb = 0); a malformed file
+    is refused and changes nothing."""
+    from paper_2101_05063_amd import Solver
+    rng = np.random.default_rng(91)
+    n = 600
+    H = g.random_hessenberg(n, rng)
+    wr, wi = np.linspace(-1.0, 1.0, 20), np.zeros(20)
+    B = np.ones((n, 20))
+    s1 = Solver(0)  # a handle of its own: one tuned entry
+    best, ms = s1.autotune([dict(H=dev(H), wr=wr, wi=wi, X=dev(B))])
+    print(f"[gpu] tuner: best nb {best}, ms {ms}", flush=True)
+    path = str(tmp_path / "tuner.txt")
+    s1.autotune_save(path)
+    s1.close()
+    s2 = Solver(0)
+    heuristic = 64  # n < 2048
+    s2.workspace(s2.workspace_size(n, wi))
+    assert s2.debug_view(n, wi)["nb"] == heuristic
+    s2.autotune_load(path)
+    assert s2.debug_view(n, wi)["nb"] == best
+    # the entry's tile size edited to the other candidate: the loaded value
+    # is what the planner uses, whichever size the timing picked
+    other = 64 if best == 128 else 128
+    lines = open(path).read().splitlines()
+    assert lines[0] == "hsrq-tuner 1" and len(lines) == 2
+    key, _ = lines[1].split()
+    open(path, "w").write(f"hsrq-tuner 1\n{key} {other}\n")
+    s2.autotune_load(path)
+    assert s2.debug_view(n, wi)["nb"] == other
+    bad = str(tmp_path / "bad.txt")
+    open(bad, "w").write("not a tuner file\n")
+    with pytest.raises(RuntimeError):
+        s2.autotune_load(bad)
+    assert s2.debug_view(n, wi)["nb"] == other
+    s2.close()

@@ -46,9 +46,11 @@ def host(T):
     return T.t().contiguous().cpu().numpy().T.copy()
 
 
-def run(solver, H, wr, wi, B, rotations, nb=0, residual=False):
-    print(f"[gpu] level-3 n={H.shape[0]} m={len(wr)} nb={nb} rotations={rotations}", flush=True)
-    Y, E, mu, info, res = solver.solve(dev(H), wr, wi, dev(B), nb=nb, residual=residual, rotations=rotations)
+def run(solver, H, wr, wi, B, rotations, nb=0, residual=False, share_min_far=0):
+    print(f"[gpu] level-3 n={H.shape[0]} m={len(wr)} nb={nb} rotations={rotations} share={share_min_far}",
+          flush=True)
+    Y, E, mu, info, res = solver.solve(dev(H), wr, wi, dev(B), nb=nb, residual=residual, rotations=rotations,
+                                       share_min_far=share_min_far)
     torch.cuda.synchronize()
     out = (host(Y), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy())
     return out + ((res.cpu().numpy(),) if residual else ())
@@ -200,3 +202,30 @@ def test_level3_graph_replay_equals_eager(solver):
     for o in outs[1:]:
         for x, y in zip(outs[0], o):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("nb", [64, 128])
+def test_shared_cu_variant(solver, nb):
+    """The critical kernel variant that shares its compute unit with a
+    far-tile block (used at full size for steps with >= 512 far-tile blocks)
+    forced on every step of a small problem (share_min_far = 1): in both forms
+    of ReduceOffdiag it gives the same bits as the variant that takes the unit
+    to itself (share_min_far = -1), and the level-3 form meets the reference
+    within the first-order bound."""
+    rng = np.random.default_rng(5100 + nb)
+    n = 700
+    H = g.random_hessenberg(n, rng)
+    h2 = np.linalg.norm(H, 2)
+    sc = np.abs(np.linalg.eigvals(H)).max()
+    wr = np.concatenate([rng.uniform(-sc, sc, 4), rng.uniform(1.5, 2.0, 4) * h2 * np.array([1, -1, 1, -1])])
+    wi = np.zeros(8)
+    wr = np.concatenate([wr, [0.2 * sc, 1.7 * h2]])
+    wi = np.concatenate([wi, [0.3 * sc, -0.4 * h2]])
+    B = rng.standard_normal((n, g.ncols(wi)))
+    for rot in (0, 1):
+        a = run(solver, H, wr, wi, B, rot, nb=nb, share_min_far=1)
+        b = run(solver, H, wr, wi, B, rot, nb=nb, share_min_far=-1)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), rot
+    ref = O.batch(H, wr, wi, B)
+    assert check_against(H, wr, wi, a, ref, "oracle") >= 4

@@ -99,6 +99,9 @@ def test_alone_equals_mix_and_reference():
     overlap = sum(1 for a in done.values() for b in done.values()
                   if a is not b and a["t_start"] < b["t_done"] and b["t_start"] < a["t_done"])
     print("overlapping request pairs:", overlap // 2)
+    # continuous batching: requests that arrive while others run are admitted
+    # and advance together (not one after another)
+    assert overlap // 2 >= 1
     for (H, wr, wi, B), A, M in zip(reqs, alone, mix):
         for x, y in zip(A, M):  # same kernels, same inputs: bit for bit
             assert np.array_equal(x, y)
@@ -160,3 +163,41 @@ def test_level3_serving_alone_equals_mix_and_single_solve():
         for x, y in zip(single, M):
             assert np.array_equal(x, y), k
     s.close()
+
+
+def test_submit_waits_for_the_callers_stream():
+    """The starting vectors are written by device work that is still queued on
+    the caller's stream when the request is submitted (a long product first,
+    then the copy into X): the server must wait for that stream, so the result
+    equals the single-problem solve of the same inputs."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_05063_amd import Server, Solver
+    reqs = requests(41, 4, 600)
+    srv = Server(0, nb=64)
+    big = torch.rand(4096, 4096, dtype=torch.float64, device="cuda")
+    outs, Xs = [], []
+    torch.cuda.synchronize()
+    for k, (H, wr, wi, B) in enumerate(reqs):
+        Hd, Bd = dev(H), dev(B)
+        torch.cuda.synchronize()
+        X = torch.full_like(Bd, float("nan"))  # stale contents if read too early
+        torch.cuda.synchronize()
+        for _ in range(3):
+            big = big @ big * (1.0 / 4096)  # keeps the stream busy for a while
+        X.copy_(Bd)  # queued behind the products
+        outs.append(srv.submit(Hd, wr, wi, X, k))
+        Xs.append((Hd, X))
+    done = drain(srv, list(range(len(reqs))))
+    assert all(c["status"] == 0 for c in done.values())
+    torch.cuda.synchronize()
+    s = Solver(0)
+    for k, ((H, wr, wi, B), (Hd, X), o) in enumerate(zip(reqs, Xs, outs)):
+        Y1 = dev(B)
+        E1, mu1, info1, _ = s.dhsrq3(dev(H), wr, wi, Y1, nb=64)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X), host(Y1)), k
+        assert np.array_equal(o[0].cpu().numpy(), E1.cpu().numpy()), k
+        assert np.array_equal(o[2].cpu().numpy(), info1.cpu().numpy()), k
+    s.close()
+    srv.close()

@@ -467,3 +467,60 @@ def test_convergence_threshold_both_sides():
         t_sq = 1 / (nn * ee * hn) ** 2
         conv = [ratio_sq(k) * nb2 / bb >= t_sq for k in (k_lo, k_hi)]
         assert conv != [True, False], what
+
+
+# ---------------------------------------------------------------------------
+# inverse iteration with restarts (Sec. 4.2, Algorithm 14)
+# ---------------------------------------------------------------------------
+def test_restart_closed_form_2x2():
+    """H = [[3, 1], [1, 3]] has the eigenvector e = (1, 1) for 4 and (1, -1)
+    for 2.  With the shift 2 + 2^-49, the all-ones start gives
+    x = e / (2 - 2^-49): no growth, not converged.  The second start
+    (1, -1)/sqrt(2), orthogonal to the first, gives x = -(1, -1) 2^49 / sqrt(2):
+    ||x|| / ||b|| = 2^49 > 1 / (10 n eps ||H||_inf) = 2^52 / 80, converged on
+    the second try, with the eigenvector (1, -1).  The norm itself is only
+    determined to about eps ||H|| / sigma_min = 2^-52 * 4 / 2^-49 relative:
+    R(1,1) is a difference of terms of size 1/sqrt(2) that cancel down to
+    about 2^-49 sqrt(2), so it is checked to 25%."""
+    H = np.array([[3.0, 1.0], [1.0, 3.0]])
+    lam = 2.0 + 2.0 ** -49
+    S = np.array([[1.0, 2 ** -0.5], [1.0, -2 ** -0.5]])
+    Y, E, mu, info, tries = O.hsrq3in(H, np.array([lam]), np.array([0.0]), S)
+    assert list(tries) == [1] and list(info) == [O.OK]
+    assert direction(Y[:, 0], np.array([1.0, -1.0])) > 1.0 - 1e-15
+    assert abs(mu[0] * 2.0 ** E[0] / 2.0 ** 49 - 1.0) <= 0.25
+    # one try only: the first start's result, flagged not converged
+    Y1, E1, mu1, info1, tries1 = O.hsrq3in(H, np.array([lam]), np.array([0.0]), S, ntries=1)
+    assert list(tries1) == [0] and list(info1) == [O.NOT_CONVERGED]
+    assert direction(Y1[:, 0], np.array([1.0, 1.0])) > 1.0 - 1e-15
+
+
+def test_restart_constant_row_sums():
+    """Rows of H summing to mu make e a right eigenvector, so every left
+    eigenvector of another eigenvalue is orthogonal to e and the all-ones
+    start cannot converge for those shifts; a start orthogonal to e does.
+    Real and complex eigenvalue shifts: all fail the first try and converge on
+    the second, to the eigenvectors numpy computes; the restart results equal
+    plain solves from the second start."""
+    n = 14
+    rng = np.random.default_rng(77)
+    H = g.constant_row_sum_hessenberg(n, rng)
+    assert np.allclose(H @ np.ones(n), 0.5)
+    import scipy.linalg as sl
+    w, vl, V = sl.eig(H, left=True, right=True)
+    cond = 1.0 / np.abs(np.sum(np.conj(vl) * V, axis=0))  # eigenvalue condition numbers
+    far = (np.abs(w - 0.5) > 0.1) & (cond < 1e6)
+    real = np.where(far & (np.abs(w.imag) < 1e-12))[0][:3]
+    cplx = np.where(far & (w.imag > 1e-12))[0][:2]
+    wr = np.concatenate([w[real].real, w[cplx].real])
+    wi = np.concatenate([np.zeros(len(real)), w[cplx].imag])
+    S = g.restart_vectors(n, 3, seed=5)
+    assert abs(S[:, 1] @ np.ones(n)) < 1e-13 and abs(S[:, 2] @ S[:, 1]) < 1e-13
+    Y, E, mu, info, tries = O.hsrq3in(H, wr, wi, S)
+    assert list(tries) == [1] * len(wr) and list(info) == [O.OK] * len(wr)
+    cols, _ = O.columns_of(wi)
+    for k, idx in enumerate(list(real) + list(cplx)):
+        y = Y[:, cols[k]] + (1j * Y[:, cols[k] + 1] if wi[k] else 0)
+        assert direction(y, V[:, idx]) > 1.0 - 1e-10
+        r = O.solve1(H, complex(wr[k], wi[k]), S[:, 1].astype(complex) if wi[k] else S[:, 1])
+        assert np.array_equal(y, r["y"]) and E[k] == r["E"] and mu[k] == r["mu"]

@@ -397,3 +397,30 @@ def c5_requests(pool, count, seed=1005, complex_frac=0.3):
         wi = np.concatenate([np.zeros(ir.size), cplx[ic].imag])
         out.append((b, wr, wi))
     return out
+
+
+def restart_vectors(n, ntries, seed=1007):
+    """Starting vectors for inverse iteration with restarts (Sec. 4.2): the
+    all-ones vector first, then ntries - 1 orthonormal vectors orthogonal to
+    it and to each other (Q of a QR factorisation of [e, G], G seeded
+    Gaussian).  n x ntries, column-major."""
+    rng = np.random.default_rng(seed)
+    A = np.concatenate([np.ones((n, 1)), rng.standard_normal((n, max(ntries - 1, 0)))], axis=1)
+    Q, _ = np.linalg.qr(A)
+    S = np.asfortranarray(Q[:, :ntries].copy())
+    S[:, 0] = 1.0
+    return S
+
+
+def constant_row_sum_hessenberg(n, rng, mu=0.5):
+    """A random unreduced Hessenberg matrix whose rows all sum to mu exactly
+    (entries rounded to multiples of 2^-12, so that every row sum is exact in
+    floating point, and the diagonal set to make them mu): H e = mu e, so
+    every left eigenvector of an eigenvalue other than mu is orthogonal to e,
+    and inverse iteration from the all-ones vector cannot converge for such a
+    shift."""
+    H = np.round(random_hessenberg(n, rng) * 4096.0) / 4096.0
+    H[np.arange(1, n), np.arange(n - 1)] = np.maximum(H[np.arange(1, n), np.arange(n - 1)], 2.0 ** -12)
+    off = np.triu(H, -1) - np.diag(np.diag(H))
+    H[np.arange(n), np.arange(n)] = mu - off.sum(axis=1)
+    return H
