@@ -59,7 +59,11 @@ enum {
     HSRQ_ERR_WORKSPACE = -1002,  /* workspace missing, too small or misaligned */
     HSRQ_ERR_ALLOC = -1003,      /* host staging allocation failed */
     HSRQ_ERR_ARG = -1004,        /* invalid argument in a batched/serving call */
-    HSRQ_ERR_BUSY = -1005        /* serving: the request does not fit the budget */
+    HSRQ_ERR_BUSY = -1005,       /* serving: the request does not fit the budget */
+    HSRQ_ERR_TOO_LARGE = -1006   /* hsrq_dhsrq3_noalloc: the problem needs more
+                                    than HSRQ_NOALLOC_SCRATCH_BYTES of workspace
+                                    (or its plan more than the handle's 2 MiB
+                                    staging buffer) */
 };
 
 typedef struct hsrq_handle_s* hsrq_handle_t;
@@ -182,6 +186,33 @@ int hsrq_dhsrq3(hsrq_handle_t h, int n, const double* H, int ldh,
                 int32_t* scale_exp, double* scale_mant, int32_t* info,
                 double* resid, void* work, size_t work_bytes,
                 const hsrq_opts_t* opts);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): hsrq_dhsrq3 with the
+ * workspace taken from a fixed device array of HSRQ_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) inside the library.  Each device the library runs on holds its
+ * own copy of the array from the first hsrq_create on it until the process
+ * ends; the call itself allocates and creates nothing (no device, pinned or
+ * graph memory, no events or streams), launches kernel by kernel on the
+ * handle's stream and stages the plan through the handle's pinned buffer.
+ *   Arguments 1-13 as for hsrq_dhsrq3 (the same statuses -1 .. -13);
+ *   opts (arg 14) as for hsrq_dhsrq3 except that precision must be 0 and
+ *   graph must not be 1 (status -14 otherwise).
+ *   Returns HSRQ_ERR_TOO_LARGE, before anything is enqueued, when the
+ *   problem's workspace (hsrq_workspace_size) exceeds the array or its plan
+ *   exceeds the handle's staging buffer.
+ * Every call on a device uses the same array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap
+ * on one device, on any handles or streams, race and give wrong results;
+ * serialise them (one stream, or synchronise between calls).
+ */
+#define HSRQ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hsrq_dhsrq3_noalloc(hsrq_handle_t h, int n, const double* H, int ldh,
+                        int m, const double* wr, const double* wi,
+                        double* X, int ldx,
+                        int32_t* scale_exp, double* scale_mant, int32_t* info,
+                        double* resid, const hsrq_opts_t* opts);
 
 /*
  * Inverse iteration with restarts (HSRQ3IN, Sec. 4.2, Algorithm 14, with

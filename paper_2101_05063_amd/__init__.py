@@ -26,9 +26,11 @@ EXPORTED = [
     "hsrq_workspace_size_batched", "hsrq_dhsrq3_batched", "hsrq_debug_view",
     "hsrq_profile_enable", "hsrq_profile_read", "hsrq_autotune", "hsrq_fallback_count",
     "hsrq_server_create", "hsrq_server_submit", "hsrq_server_poll", "hsrq_server_clock", "hsrq_server_destroy",
-    "hsrq_hsrq3in_workspace_size", "hsrq_hsrq3in",
+    "hsrq_dhsrq3_noalloc", "hsrq_hsrq3in_workspace_size", "hsrq_hsrq3in",
     "hsrq_autotune_save", "hsrq_autotune_load",
 ]
+HSRQ_ERR_TOO_LARGE = -1006
+NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_KINDS = ["prep", "init", "crit", "far", "final", "output", "resid"]
 
 
@@ -81,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_server_poll.argtypes = [vp, P(HsrqCompletion), i, P(i), i]
     lib.hsrq_server_clock.argtypes = [vp, P(ctypes.c_double)]
     lib.hsrq_server_destroy.argtypes = [vp]
+    lib.hsrq_dhsrq3_noalloc.argtypes = [vp, i, vp, i, i, vp, vp, vp, i, vp, vp, vp, vp, P(HsrqOpts)]
     lib.hsrq_autotune_save.argtypes = [vp, ctypes.c_char_p]
     lib.hsrq_autotune_load.argtypes = [vp, ctypes.c_char_p]
     lib.hsrq_hsrq3in_workspace_size.argtypes = [vp, i, i, vp, P(HsrqOpts), P(sz)]
@@ -210,6 +213,35 @@ class Solver:
         _check(st, "hsrq_dhsrq3")
         self._keep = (Hc,)  # keep a temporary column-major copy alive until the stream runs
         return E, mu, info, res
+
+    def dhsrq3_noalloc(self, H, wr, wi, X, nb=0, residual=False, stream=None, rotations=0, share_min_far=0):
+        """As dhsrq3 (precision 0, kernel by kernel) with the library's fixed
+        device scratch array as the workspace: the library allocates nothing.
+        Returns (status, scale_exp, scale_mant, info, resid); status is
+        HSRQ_ERR_TOO_LARGE when the problem does not fit the array.  Calls on
+        one device must not overlap (they share the array)."""
+        torch = self.torch
+        n = H.shape[0]
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        m = wr.shape[0]
+        Hc, ldh = colmajor(H)
+        if X.shape[0] > 1 and X.stride(0) != 1:
+            raise ValueError("X must be column-major (X.stride(0) == 1)")
+        ldx = max(X.stride(1) if X.shape[1] > 1 else n, n)
+        dev = H.device
+        E = torch.empty(m, dtype=torch.int32, device=dev)
+        mu = torch.empty(m, dtype=torch.float64, device=dev)
+        info = torch.empty(m, dtype=torch.int32, device=dev)
+        res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
+        o = _opts(nb, 0, residual, -1, rotations, share_min_far)
+        self._stream(stream)
+        st = self.lib.hsrq_dhsrq3_noalloc(self.h, n, Hc.data_ptr(), ldh, m, wr.ctypes.data_as(ctypes.c_void_p),
+                                          wi.ctypes.data_as(ctypes.c_void_p), X.data_ptr(), ldx, E.data_ptr(),
+                                          mu.data_ptr(), info.data_ptr(),
+                                          res.data_ptr() if res is not None else None, ctypes.byref(o))
+        self._keep = (Hc,)
+        return st, E, mu, info, res
 
     def hsrq3in(self, H, wr, wi, S, nb=0, residual=False, stream=None, rotations=0, work_bytes=None):
         """Inverse iteration with restarts (hsrq_hsrq3in): S (device, n x

@@ -879,7 +879,29 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
 
 namespace hsrq {
 
+int handle_device(hsrq_handle_t h) { return h->device; }
 bool opts_valid(const hsrq_opts_t* o) { return opts_ok(o); }
+
+// The single-problem solve (precision 0) in the given workspace with nothing
+// allocated or created: kernel-by-kernel launches on the handle's stream and
+// its second stream, the plan staged through the handle's pinned buffer
+// (created with the handle), no graph, no profiling events.
+int run_noalloc(hsrq_handle_t h, const hsrq_problem_t& p, void* work, size_t work_bytes, const hsrq_opts_t* o) {
+  Plan P;
+  build_plan(P, 1, &p, choose_nb(h, 1, &p, o));
+  P.l3rot = o ? o->rotations : 0;
+  P.share = share_min(o);
+  if (work_bytes < P.total_bytes || P.head_bytes > h->staging_bytes) return HSRQ_ERR_TOO_LARGE;
+  if (h->staging_pending) {
+    if (hipEventSynchronize(h->staging_ev) != hipSuccess) return HSRQ_ERR_HIP;
+    h->staging_pending = false;
+  }
+  fill_staging(P, 1, &p, work, o, static_cast<char*>(h->staging));
+  const int st = enqueue(h, P, 1, work, h->staging, h->stream, wants_residual(o, 1, &p), true, false,
+                         h->staging_ev);
+  h->staging_pending = true;
+  return st;
+}
 
 }  // namespace hsrq
 
@@ -1101,11 +1123,13 @@ int hsrq_create(hsrq_handle_t* out, int device) {
   if (!h) return HSRQ_ERR_ALLOC;
   h->device = device;
   // everything a solve needs on the host side is created here: the staging
-  // buffer, the second stream and its events
+  // buffer, the second stream and its events, and the device's scratch
+  // address for hsrq_dhsrq3_noalloc
   int st = HSRQ_OK;
   if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) st = HSRQ_ERR_HIP;
   if (st == HSRQ_OK) st = create_sync(h);
   if (st == HSRQ_OK) st = ensure_staging(h, kStagingBytes);
+  if (st == HSRQ_OK && scratch_init(device) != 0) st = HSRQ_ERR_HIP;
   if (st) {
     hsrq_destroy(h);
     return st;

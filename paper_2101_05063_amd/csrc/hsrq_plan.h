@@ -91,6 +91,11 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
 int check_problem(const hsrq_problem_t& p);
 // options outside their documented values
 bool opts_valid(const hsrq_opts_t* o);
+// scratch for hsrq_dhsrq3_noalloc (hsrq_noalloc.hip): scratch_init records
+// the address of the device's copy (once per device, with it current)
+int scratch_init(int device);
+int handle_device(hsrq_handle_t h);
+int run_noalloc(hsrq_handle_t h, const hsrq_problem_t& p, void* work, size_t work_bytes, const hsrq_opts_t* o);
 
 
 template <class T>
