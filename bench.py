@@ -72,11 +72,13 @@ def table1_flops(n, nb, wi):
 
 
 def kernel_source_hash():
+    """Hash of the device-code sources (the kernels and the layout header
+    they share): counter figures are valid only for the kernels they were
+    taken on."""
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2101_05063_amd", "csrc")
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(src, f), "rb").read())
+    for f in ("hsrq_kernels.hip", "hsrq_common.h"):
+        h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -141,6 +143,49 @@ def ingest_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes)
     d = {"kernel_source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
          "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
     with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps(d, indent=1, sort_keys=True))
+
+
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_c3.json")
+
+
+def ingest_mfma(pmc_csv, stats_csv):
+    """Writes profiles/mfma_c3.json from a rocprofv3 counter run of the
+    benchmark (SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64,
+    SQ_WAIT_INST_ANY, SQ_WAVE_CYCLES) and the kernel statistics of a
+    kernel-trace run of the same command: per kernel the MFMA flops per
+    launch (MOPS_F64 counts units of 512 flops) and the fraction of the
+    1024 SIMDs' cycles over the average launch duration that the matrix
+    cores were busy."""
+    import csv
+    import statistics
+    acc = {}
+    with open(pmc_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            key = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            d = acc.setdefault(key, {}).setdefault(r["Counter_Name"], {})
+            d.setdefault(r.get("Dispatch_Id", str(len(d))), 0.0)
+            d[r.get("Dispatch_Id", str(len(d)))] += float(r["Counter_Value"])
+    avg_ns = {}
+    with open(stats_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            avg_ns[r["Name"].split("(")[0].replace("void ", "").strip()] = float(r["AverageNs"])
+    kernels = {}
+    for k, cs in acc.items():
+        if k not in avg_ns or "SQ_VALU_MFMA_BUSY_CYCLES" not in cs:
+            continue
+        mean = {c: statistics.mean(v.values()) for c, v in cs.items()}
+        busy = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (1024 * 2.4e9 * avg_ns[k] * 1e-9)
+        ent = {"avg_launch_us": avg_ns[k] / 1e3, "mfma_busy": round(busy, 4),
+               "dispatches": len(next(iter(cs.values())))}
+        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in mean:
+            ent["mfma_flops_per_launch"] = mean["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512.0
+        if "SQ_WAIT_INST_ANY" in mean and "SQ_WAVE_CYCLES" in mean and mean["SQ_WAVE_CYCLES"] > 0:
+            ent["wave_cycles_waiting"] = round(mean["SQ_WAIT_INST_ANY"] / mean["SQ_WAVE_CYCLES"], 4)
+        kernels[k] = ent
+    d = {"kernel_source_hash": kernel_source_hash(), "kernels": kernels}
+    with open(MFMA_FILE, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
     print(json.dumps(d, indent=1, sort_keys=True))
 
@@ -296,7 +341,7 @@ def bench_c4(args):
     def problems():
         return [dict(H=H, wr=p["wr"], wi=p["wi"], X=B.clone()) for H, B, p in zip(Hs, Bs, probs_h)]
 
-    best, tune_ms = solver.autotune(problems(), precision=args.precision, rotations=args.rotations)
+    best, best_cb, tune_ms = solver.autotune(problems(), precision=args.precision, rotations=args.rotations)
 
     def timed(graph):
         sets = [problems() for _ in range(args.warmup + args.steps)]
@@ -326,7 +371,9 @@ def bench_c4(args):
                    "matrices": len(probs_h), "sum_n": int(sum(p["H"].shape[0] for p in probs_h)),
                    "shifts": nshift, "columns": ncols, "precision": args.precision,
                    "rotations": args.rotations,
-                   "autotuned_nb": best, "autotune_ms": tune_ms, "graph": args.precision == 0},
+                   "autotuned_nb": best, "autotuned_cols_per_block": best_cb,
+                   "autotune_ms": {f"nb={nb},cols_per_block={cb}": round(v, 4) for (nb, cb), v in tune_ms.items()},
+                   "graph": args.precision == 0},
         "shifts_per_s": round(nshift / (ms * 1e-3), 2),
         "ms_per_step_kernel_by_kernel": round(ms_eager, 4),
         "converged_fraction": conv,
@@ -473,7 +520,12 @@ def main():
                     help="run only a plain device copy of known size (counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write profiles/traffic_c3.json from rocprofv3 counter_collection.csv files")
+    ap.add_argument("--ingest-mfma", nargs=2, metavar=("PMC_CSV", "KERNEL_STATS_CSV"),
+                    help="write profiles/mfma_c3.json from a counter run and the kernel statistics of a trace run")
     args = ap.parse_args()
+    if args.ingest_mfma:
+        ingest_mfma(*args.ingest_mfma)
+        return
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc, COPY_BYTES)
         return
@@ -565,10 +617,9 @@ def main():
 def mfma_counters():
     """MFMA-busy fractions per kernel from the committed counter run (valid
     only for the kernel sources it was taken on), or {}."""
-    path = os.path.join(ROOT, "profiles", "mfma_c3.json")
-    if not os.path.exists(path):
+    if not os.path.exists(MFMA_FILE):
         return {}
-    d = json.load(open(path))
+    d = json.load(open(MFMA_FILE))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return {}
     return d.get("kernels", {})
@@ -626,7 +677,8 @@ def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
         if kind == "far":
-            name = f"hsrq::k_far3<{nbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
+            # the library's default far-block width (64 columns) at this size
+            name = f"hsrq::k_far3<{nbv}, 64>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
         else:
             # steps with many far-tile blocks use the variant that shares its CU
             tmpl = f"<{nbv}, {f32}, {'true' if l3 else 'false'}>"

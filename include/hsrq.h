@@ -75,12 +75,15 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 set if it ran on the handle, else 128 when the largest
  *                 order is >= 2048 and 64 otherwise.
  *   Any other value of nb, precision (0, 1), residual (0, 1), graph
- *   (-1, 0, 1), rotations (0, 1) or share_min_far (>= -1) makes the call
+ *   (-1, 0, 1), rotations (0, 1), share_min_far (>= -1) or cols_per_block
+ *   (0, 64; 32 with rotations 1 and precision 0) makes the call
  *   fail with the position of opts (LAPACK style: -16 for hsrq_dhsrq3, -5
  *   for hsrq_workspace_size) or HSRQ_ERR_ARG for the batched, tuning and
  *   debug calls; nothing is substituted silently.
- *   cols_per_block reserved (shift blocks are fixed by the kernels: 64
- *                 columns per far-tile block, 16 per critical block).
+ *   cols_per_block columns (shifts) per far-tile block, the b_c of Sec. 3.2:
+ *                 64, or 32 in the level-3 form (rotations 1, precision 0);
+ *                 0 = the tuner's choice for this problem set if it ran,
+ *                 else 64.  Critical blocks always take 8 columns.
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
  *                 matrix cores, then an FP64 residual check per shift with a
  *                 fall back to the all-FP64 solve for shifts that fail it.
@@ -256,6 +259,31 @@ int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
                  int32_t* tries, double* resid, void* work, size_t work_bytes,
                  const hsrq_opts_t* opts);
 
+/*
+ * The steps around the solve (Sec. 1): a general real matrix A is reduced to
+ * upper Hessenberg form H = Q0^T A Q0, and an eigenvector x of H becomes the
+ * eigenvector z = Q0 x of A.  Q0 = H_0 H_1 ... H_{n-3}, H_k = I - tau_k u_k
+ * u_k^T, u_k zero above row k+1, u_k(k+1) = 1; the layout is LAPACK's DGEHRD
+ * one, with H_k A(k+1:n, k) = beta e_1 and beta = -sign(A(k+1, k)) times the
+ * norm of A(k+1:n, k).  Unblocked (one reflector at a time, each applied
+ * with matrix-vector and rank-1 kernels), asynchronous on the handle's
+ * stream, workspace from the caller (256-byte aligned).
+ *
+ * hsrq_gehrd: A (device, n x n, lda >= n) in: general; out: H on and above
+ *   the first subdiagonal, u_k(k+2:n) below it in column k.  tau (device,
+ *   n - 1 entries; tau[n-2] = 0).  The result can be passed as the H of
+ *   hsrq_dhsrq3 as it is (only the Hessenberg part is read there).
+ *   Statuses -1 .. -6 for an invalid h, n, A, lda, tau, work.
+ * hsrq_ormhr: Z (device, n x ncols, ldz >= n) <- Q0 Z, with A and tau as
+ *   hsrq_gehrd left them.  Statuses -1 .. -9 for an invalid h, n, A, lda,
+ *   tau, ncols, Z, ldz, work.
+ */
+int hsrq_gehrd_workspace_size(hsrq_handle_t h, int n, size_t* bytes);
+int hsrq_gehrd(hsrq_handle_t h, int n, double* A, int lda, double* tau, void* work, size_t work_bytes);
+int hsrq_ormhr_workspace_size(hsrq_handle_t h, int n, int ncols, size_t* bytes);
+int hsrq_ormhr(hsrq_handle_t h, int n, const double* A, int lda, const double* tau, int ncols, double* Z, int ldz,
+               void* work, size_t work_bytes);
+
 /* Workspace query for hsrq_dhsrq3_batched (problems: host array of count
    descriptors; only n, m and wi are read). */
 int hsrq_workspace_size_batched(hsrq_handle_t h, int count, const hsrq_problem_t* problems,
@@ -290,21 +318,24 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
 int hsrq_fallback_count(hsrq_handle_t h, int64_t* count);
 
 /*
- * Autotuner (tile size b_r).  Runs the solve of the given problem set once
- * per candidate tile size (64, 128) that fits the workspace, timed with HIP
- * events on the handle's stream, and records the fastest for this problem
- * set (keyed by the orders and column counts of its problems) in the handle:
- * later calls with opts->nb == 0 on a problem set of the same shape use it.
- * The caller's X, residuals and starting vectors are left untouched;
- * scale_exp, scale_mant and info receive the results of a candidate run.
- * Synchronises the handle's stream.  *best_nb (host) receives the choice;
- * ms (host, length 2, may be NULL) the measured milliseconds per candidate
- * (0 for a candidate that did not fit).  work as for hsrq_dhsrq3_batched,
- * sized with opts->nb == 0; opts (may be NULL) as for the solve (its nb and
- * graph fields are ignored).  Returns HSRQ_ERR_WORKSPACE if no candidate fits.
+ * Autotuner (tile size b_r and far-block width b_c, Sec. 3.2).  Runs the
+ * solve of the given problem set once per candidate pair (b_r in {64, 128},
+ * b_c in {32, 64} for the level-3 form, b_c = 64 otherwise) that fits the
+ * workspace, timed with HIP events on the handle's stream, and records the
+ * fastest for this problem set (keyed by the orders and column counts of its
+ * problems) in the handle: later calls with opts->nb == 0 use its b_r, and
+ * with opts->cols_per_block == 0 its b_c.  The caller's X, residuals and
+ * starting vectors are left untouched; scale_exp, scale_mant and info
+ * receive the results of a candidate run.  Synchronises the handle's stream.
+ * *best_nb and *best_cb (host; best_cb may be NULL) receive the choice; ms
+ * (host, length 4, may be NULL) the measured milliseconds per candidate at
+ * index 2 (b_r == 128) + (b_c == 64) (0 for a candidate not run).  work as
+ * for hsrq_dhsrq3_batched, sized with opts->nb == 0; opts (may be NULL) as
+ * for the solve (its nb, cols_per_block and graph fields are ignored).
+ * Returns HSRQ_ERR_WORKSPACE if no candidate fits.
  */
 int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work, size_t work_bytes,
-                  const hsrq_opts_t* opts, int* best_nb, double* ms);
+                  const hsrq_opts_t* opts, int* best_nb, int* best_cb, double* ms);
 
 /*
  * Tuner cache.  hsrq_autotune_save writes the handle's tuned choices (one per

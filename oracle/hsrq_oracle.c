@@ -25,7 +25,7 @@
  *   and s real (the convention of eq. cgivens); everything else in complex
  *   arithmetic.
  *
- * Readings of the paper taken here (see the design doc of the repository):
+ * Readings of the paper taken here (where it is silent or ambiguous):
  *   - Givens convention: r = hypot(a, |v|) >= 0, c = v / r, s = -a / r, so
  *     [a v] G = [0 r] and every R(k,k), k >= 2, is r > 0.  The hypot is
  *     written out: scale by 2^-ilogb(max), sqrt(fma(a,a, fma(vr,vr, vi*vi))),

@@ -199,3 +199,53 @@ def hsrq3in(H, wr, wi, S, ntries=None):
             E[l], mu[l], info[l], tries[l] = Ea[k], mua[k], infoa[k], t
         act = [l for k, l in enumerate(act) if infoa[k] == NOT_CONVERGED]
     return Y, E, mu, info, tries
+
+
+def hessenberg_reduce(A):
+    """Householder reduction to upper Hessenberg form, H = Q0^T A Q0 (the
+    step before the solve, Sec. 1), one column at a time in plain numpy.
+
+    For k = 0 .. n-3 the reflector H_k = I - tau_k u u^T, u = [1; v], maps
+    x = A(k+1:n, k) to beta e_1 with beta = -sign(x_1) ||x|| (so x_1 - beta
+    does not cancel): tau_k = (beta - x_1) / beta, v = x(2:) / (x_1 - beta).
+    It is applied from the right to A(:, k+1:n), then from the left to
+    A(k+1:n, k+1:n).  Returns (R, tau) in LAPACK's DGEHRD layout: H on and
+    above the first subdiagonal of R, v below it in column k; tau has n - 1
+    entries, the last 0.
+    """
+    R = np.array(A, dtype=np.float64, order="F", copy=True)
+    n = R.shape[0]
+    tau = np.zeros(max(n - 1, 1))
+    for k in range(n - 2):
+        x = R[k + 1:, k].copy()
+        alpha = x[0]
+        xnorm = np.linalg.norm(x[1:])
+        if xnorm == 0.0:
+            continue
+        beta = -np.copysign(np.hypot(alpha, xnorm), alpha)
+        t = (beta - alpha) / beta
+        v = x[1:] / (alpha - beta)
+        u = np.concatenate([[1.0], v])
+        # from the right, then from the left
+        R[:, k + 1:] -= t * np.outer(R[:, k + 1:] @ u, u)
+        R[k + 1:, k + 1:] -= t * np.outer(u, u @ R[k + 1:, k + 1:])
+        R[k + 1, k] = beta
+        R[k + 2:, k] = v
+        tau[k] = t
+    return R, tau
+
+
+def hessenberg_part(R):
+    """H from the layout of hessenberg_reduce (zeros below the subdiagonal)."""
+    return np.triu(R, -1)
+
+
+def apply_q(R, tau, Z):
+    """Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z))) from the reflectors of
+    hessenberg_reduce (the back-transform z = Q0 x of Sec. 1)."""
+    Z = np.array(Z, dtype=np.float64, copy=True)
+    n = R.shape[0]
+    for k in range(n - 3, -1, -1):
+        u = np.concatenate([[1.0], R[k + 2:, k]])
+        Z[k + 1:] -= tau[k] * np.outer(u, u @ Z[k + 1:])
+    return Z

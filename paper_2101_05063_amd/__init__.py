@@ -28,6 +28,7 @@ EXPORTED = [
     "hsrq_server_create", "hsrq_server_submit", "hsrq_server_poll", "hsrq_server_clock", "hsrq_server_destroy",
     "hsrq_dhsrq3_noalloc", "hsrq_hsrq3in_workspace_size", "hsrq_hsrq3in",
     "hsrq_autotune_save", "hsrq_autotune_load",
+    "hsrq_gehrd_workspace_size", "hsrq_gehrd", "hsrq_ormhr_workspace_size", "hsrq_ormhr",
 ]
 HSRQ_ERR_TOO_LARGE = -1006
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -76,7 +77,7 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_debug_view.argtypes = [vp, i, i, vp, P(HsrqOpts), vp, P(vp), P(vp), P(vp), P(vp), P(i), P(i), vp]
     lib.hsrq_profile_enable.argtypes = [vp, i]
     lib.hsrq_profile_read.argtypes = [vp, i, vp, vp]
-    lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), vp]
+    lib.hsrq_autotune.argtypes = [vp, i, P(HsrqProblem), vp, sz, P(HsrqOpts), P(i), P(i), vp]
     lib.hsrq_fallback_count.argtypes = [vp, P(ctypes.c_int64)]
     lib.hsrq_server_create.argtypes = [P(vp), i, sz, P(HsrqOpts)]
     lib.hsrq_server_submit.argtypes = [vp, P(HsrqProblem), ctypes.c_uint64, vp]
@@ -84,6 +85,10 @@ def load_library(path: str = LIB_PATH):
     lib.hsrq_server_clock.argtypes = [vp, P(ctypes.c_double)]
     lib.hsrq_server_destroy.argtypes = [vp]
     lib.hsrq_dhsrq3_noalloc.argtypes = [vp, i, vp, i, i, vp, vp, vp, i, vp, vp, vp, vp, P(HsrqOpts)]
+    lib.hsrq_gehrd_workspace_size.argtypes = [vp, i, P(sz)]
+    lib.hsrq_gehrd.argtypes = [vp, i, vp, i, vp, vp, sz]
+    lib.hsrq_ormhr_workspace_size.argtypes = [vp, i, i, P(sz)]
+    lib.hsrq_ormhr.argtypes = [vp, i, vp, i, vp, i, vp, i, vp, sz]
     lib.hsrq_autotune_save.argtypes = [vp, ctypes.c_char_p]
     lib.hsrq_autotune_load.argtypes = [vp, ctypes.c_char_p]
     lib.hsrq_hsrq3in_workspace_size.argtypes = [vp, i, i, vp, P(HsrqOpts), P(sz)]
@@ -106,9 +111,10 @@ def _check(st, what):
         raise RuntimeError(f"{what} failed with status {st}")
 
 
-def _opts(nb=0, precision=0, residual=False, graph=0, rotations=0, share_min_far=0):
+def _opts(nb=0, precision=0, residual=False, graph=0, rotations=0, share_min_far=0, cols_per_block=0):
     o = HsrqOpts()
     o.nb = int(nb or 0)
+    o.cols_per_block = int(cols_per_block)
     o.precision = int(precision)
     o.residual = 1 if residual else 0
     o.graph = int(graph)
@@ -171,22 +177,22 @@ class Solver:
         aligned = (base + 255) & ~255
         return aligned, self._ws.numel() - (aligned - base)
 
-    def workspace_size(self, n, wi, nb=0, precision=0):
+    def workspace_size(self, n, wi, nb=0, precision=0, rotations=0):
         wi = np.ascontiguousarray(wi, dtype=np.float64)
-        o = _opts(nb, precision)
+        o = _opts(nb, precision, rotations=rotations)
         out = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size(self.h, n, wi.shape[0], wi.ctypes.data_as(ctypes.c_void_p),
                                             ctypes.byref(o), ctypes.byref(out)), "hsrq_workspace_size")
         return out.value
 
     def dhsrq3(self, H, wr, wi, X, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0,
-               share_min_far=0):
+               share_min_far=0, cols_per_block=0):
         """Solve in place: X (device, n x ncols) holds the starting vectors and
         receives the unit vectors.  Returns (scale_exp, scale_mant, info,
         resid) device tensors of length m.  rotations=1 applies the
         off-diagonal rotations of a tile column as one product on the matrix
         cores (default 0: one at a time, bit-identical to Alg. 1's order).
-        share_min_far: see hsrq_opts_t (0 = library default)."""
+        share_min_far, cols_per_block: see hsrq_opts_t (0 = library default)."""
         torch = self.torch
         n = H.shape[0]
         wr = np.ascontiguousarray(wr, dtype=np.float64)
@@ -202,8 +208,8 @@ class Solver:
         mu = torch.empty(m, dtype=torch.float64, device=dev)
         info = torch.empty(m, dtype=torch.int32, device=dev)
         res = torch.empty(m, dtype=torch.float64, device=dev) if residual else None
-        o = _opts(nb, precision, residual, graph, rotations, share_min_far)
-        need = self.workspace_size(n, wi, nb, precision)
+        o = _opts(nb, precision, residual, graph, rotations, share_min_far, cols_per_block)
+        need = self.workspace_size(n, wi, nb, precision, rotations)
         wp, wb = self.workspace(need)
         self._stream(stream)
         st = self.lib.hsrq_dhsrq3(self.h, n, Hc.data_ptr(), ldh, m, wr.ctypes.data_as(ctypes.c_void_p),
@@ -315,14 +321,14 @@ class Solver:
         return arr, keep, outs
 
     def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0,
-                share_min_far=0):
+                share_min_far=0, cols_per_block=0):
         """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
         solved in place).  Returns a list of (E, mu, info, resid).  graph: 1
         replay as a HIP graph, -1 launch kernel by kernel, 0 library default
         (graph)."""
         count = len(problems)
         arr, keep, outs = self._problem_array(problems, residual)
-        o = _opts(nb, precision, residual, graph, rotations, share_min_far)
+        o = _opts(nb, precision, residual, graph, rotations, share_min_far, cols_per_block)
         need = ctypes.c_size_t()
         _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
                "hsrq_workspace_size_batched")
@@ -334,9 +340,10 @@ class Solver:
         return outs
 
     def autotune(self, problems, precision=0, stream=None, rotations=0):
-        """Times each tile size on this problem set and records the fastest in
-        the handle (used by later calls with nb=0).  Returns (best_nb,
-        {nb: ms}).  The problems' X are not modified."""
+        """Times each (tile size, far-block width) on this problem set and
+        records the fastest in the handle (used by later calls with nb=0 and
+        cols_per_block=0).  Returns (best_nb, best_cb, {(nb, cb): ms}) with
+        ms 0 for a pair not run.  The problems' X are not modified."""
         count = len(problems)
         arr, keep, outs = self._problem_array(problems, False)
         o = _opts(0, precision, rotations=rotations)
@@ -345,11 +352,47 @@ class Solver:
                "hsrq_workspace_size_batched")
         wp, wb = self.workspace(need.value)
         self._stream(stream)
-        best = ctypes.c_int()
-        ms = np.zeros(2)
+        best, best_cb = ctypes.c_int(), ctypes.c_int()
+        ms = np.zeros(4)
         _check(self.lib.hsrq_autotune(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o),
-                                      ctypes.byref(best), ms.ctypes.data_as(ctypes.c_void_p)), "hsrq_autotune")
-        return best.value, {64: float(ms[0]), 128: float(ms[1])}
+                                      ctypes.byref(best), ctypes.byref(best_cb),
+                                      ms.ctypes.data_as(ctypes.c_void_p)), "hsrq_autotune")
+        grid = {(nb, cb): float(ms[2 * (nb == 128) + (cb == 64)]) for nb in (64, 128) for cb in (32, 64)}
+        return best.value, best_cb.value, grid
+
+    def gehrd(self, A, stream=None):
+        """Reduce A (device, n x n, column-major, modified in place) to upper
+        Hessenberg form H = Q0^T A Q0 (hsrq_gehrd).  Returns tau (device,
+        n - 1); A then holds H and the reflectors below its subdiagonal."""
+        torch = self.torch
+        n = A.shape[0]
+        if A.shape[0] != A.shape[1] or (n > 1 and A.stride(0) != 1):
+            raise ValueError("A must be square and column-major")
+        lda = max(A.stride(1), n) if n > 1 else 1
+        tau = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=A.device)
+        need = ctypes.c_size_t()
+        _check(self.lib.hsrq_gehrd_workspace_size(self.h, n, ctypes.byref(need)), "hsrq_gehrd_workspace_size")
+        wp, wb = self.workspace(need.value)
+        self._stream(stream)
+        _check(self.lib.hsrq_gehrd(self.h, n, A.data_ptr(), lda, tau.data_ptr(), ctypes.c_void_p(wp), wb),
+               "hsrq_gehrd")
+        return tau
+
+    def ormhr(self, A, tau, Z, stream=None):
+        """Z <- Q0 Z in place (hsrq_ormhr), A and tau as gehrd left them."""
+        n = A.shape[0]
+        if Z.shape[0] > 1 and Z.stride(0) != 1:
+            raise ValueError("Z must be column-major")
+        lda = max(A.stride(1), n) if n > 1 else 1
+        ldz = max(Z.stride(1) if Z.shape[1] > 1 else n, n)
+        need = ctypes.c_size_t()
+        _check(self.lib.hsrq_ormhr_workspace_size(self.h, n, Z.shape[1], ctypes.byref(need)),
+               "hsrq_ormhr_workspace_size")
+        wp, wb = self.workspace(need.value)
+        self._stream(stream)
+        _check(self.lib.hsrq_ormhr(self.h, n, A.data_ptr(), lda, tau.data_ptr(), Z.shape[1], Z.data_ptr(), ldz,
+                                   ctypes.c_void_p(wp), wb), "hsrq_ormhr")
+        return Z
 
     def autotune_save(self, path):
         """Write the handle's tuned choices to a text file (hsrq_autotune_save)."""
@@ -410,7 +453,7 @@ class Server:
     poll() has returned the request's tag."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 200 * 10 ** 9, nb: int = 0, precision: int = 0,
-                 residual: bool = False, rotations: int = 0):
+                 residual: bool = False, rotations: int = 0, cols_per_block: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP library has no CPU fallback")
@@ -418,7 +461,7 @@ class Server:
         self.lib = load_library()
         self.residual = residual
         h = ctypes.c_void_p()
-        o = _opts(nb, precision, residual, rotations=rotations)
+        o = _opts(nb, precision, residual, rotations=rotations, cols_per_block=cols_per_block)
         _check(self.lib.hsrq_server_create(ctypes.byref(h), device, int(budget_bytes), ctypes.byref(o)),
                "hsrq_server_create")
         self.h = h

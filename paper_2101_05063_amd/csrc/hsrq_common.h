@@ -30,9 +30,14 @@ enum FlagBits : int32_t { FL_NONFINITE = 1, FL_REDUCED = 2 };
 struct ProbDesc {
   const double* H;
   long long ldh;
-  int n, N, nb, ncols, ld, nblk, m, precision;
+  int n, N, nb, ncols, ld, nblk, nfblk, m, precision;  // nfblk: far-tile column blocks
   // workspace (device)
-  double *V, *X, *Y, *C, *S, *PHI, *Z0, *Z1, *W0, *W1;
+  double *V, *X, *Y, *C, *S, *PHI;
+  // Z and W panels, two per problem: the critical task of step t writes
+  // slot t & 1 and the tasks of step t + 1 read it (every task of step t + 1
+  // has finished before step t + 2 writes the slot again)
+  double* Z[2];
+  double* W[2];
   double *BMAX, *VMAX, *BSSQ, *BCMX, *TN, *FIN;
   int32_t *AX, *AMAX;
   // partial sums written once per call and reduced in a fixed order, so that
@@ -73,6 +78,9 @@ struct CopyEnt {
   void* dst;
   long long nbytes;
 };
+
+// the Z / W panel slot written by the critical task of step t
+__host__ __device__ inline int zw_slot(int t) { return t & 1; }
 
 __host__ __device__ inline int tile_end(int n, int N, int nb, int t) { return n - (N - 1 - t) * nb; }
 __host__ __device__ inline int tile_start(int n, int N, int nb, int t) {

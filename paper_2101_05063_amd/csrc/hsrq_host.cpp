@@ -80,8 +80,9 @@ void xcd_order(Task* t, int n) {
   }
 }
 
-void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) {
+void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice, int fcb) {
   P.nb = nb_choice;
+  P.fcb = fcb;
   const int nb = P.nb;
   P.pp.resize(count);
   int Tmax = 0;
@@ -94,6 +95,7 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.ncols = q.lay.ncols;
     q.ld = std::max(8, (q.ncols + 7) & ~7);
     q.nblk = (q.ncols + kCB - 1) / kCB;
+    q.nfblk = (q.ncols + fcb - 1) / fcb;
     if (q.ncols > 0) Tmax = std::max(Tmax, q.N);
     P.nmax = std::max(P.nmax, q.n);
   }
@@ -124,7 +126,7 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
         if (q.ncols == 0 || q.N <= t) continue;
         const int jt = q.N - t;
         for (int i = 0; i < jt - 1; ++i)
-          for (int L = 0; L < q.nblk; ++L) P.tasks.push_back(Task{p, task_code(TK_FAR, t), i, L});
+          for (int L = 0; L < q.nfblk; ++L) P.tasks.push_back(Task{p, task_code(TK_FAR, t), i, L});
       }
     }
     P.fcnt[t] = (int)P.tasks.size() - P.foff[t];
@@ -177,10 +179,10 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice) 
     q.o_C = off; off = align_up(off + vec);
     q.o_S = off; off = align_up(off + vec);
     q.o_PHI = off; off = align_up(off + vec);
-    q.o_Z0 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
-    q.o_Z1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
-    q.o_W0 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 1) * q.ld);
-    q.o_W1 = off; off = align_up(off + sizeof(double) * (size_t)(nb + 1) * q.ld);
+    for (int k = 0; k < 2; ++k) {
+      q.o_Z[k] = off; off = align_up(off + sizeof(double) * (size_t)(nb + 3) * q.ld);
+      q.o_W[k] = off; off = align_up(off + sizeof(double) * (size_t)(nb + 1) * q.ld);
+    }
     q.o_BMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_VMAX = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
     q.o_BSSQ = off; off = align_up(off + sizeof(double) * (size_t)q.N * q.ld);
@@ -210,7 +212,7 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
     std::memset(&d, 0, sizeof(d));
     d.H = pr.H;
     d.ldh = pr.ldh;
-    d.n = q.n; d.N = q.N; d.nb = q.nb; d.ncols = q.ncols; d.ld = q.ld; d.nblk = q.nblk; d.m = pr.m;
+    d.n = q.n; d.N = q.N; d.nb = q.nb; d.ncols = q.ncols; d.ld = q.ld; d.nblk = q.nblk; d.nfblk = q.nfblk; d.m = pr.m;
     d.precision = o ? o->precision : 0;
     d.V = at<double>(work, q.o_V);
     d.X = at<double>(work, q.o_X);
@@ -218,10 +220,10 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
     d.C = at<double>(work, q.o_C);
     d.S = at<double>(work, q.o_S);
     d.PHI = at<double>(work, q.o_PHI);
-    d.Z0 = at<double>(work, q.o_Z0);
-    d.Z1 = at<double>(work, q.o_Z1);
-    d.W0 = at<double>(work, q.o_W0);
-    d.W1 = at<double>(work, q.o_W1);
+    for (int k = 0; k < 2; ++k) {
+      d.Z[k] = at<double>(work, q.o_Z[k]);
+      d.W[k] = at<double>(work, q.o_W[k]);
+    }
     d.BMAX = at<double>(work, q.o_BMAX);
     d.VMAX = at<double>(work, q.o_VMAX);
     d.BSSQ = at<double>(work, q.o_BSSQ);
@@ -320,8 +322,12 @@ struct hsrq_handle_s {
   };
   std::vector<GraphEntry> graphs;
   uint64_t stamp = 0;
-  // autotuner results: problem-set signature -> tile size
-  std::vector<std::pair<uint64_t, int>> tuned;
+  // autotuner results: problem-set signature -> tile size, far-block width
+  struct Tuned {
+    uint64_t key;
+    int nb, fcb;
+  };
+  std::vector<Tuned> tuned;
   // mixed precision: shifts re-solved in FP64 by the last call, and a pinned
   // buffer for the gather/scatter lists (read by the copy kernel in place)
   size_t last_fallback = 0;
@@ -373,19 +379,31 @@ bool opts_ok(const hsrq_opts_t* o) {
   if (o->graph < -1 || o->graph > 1) return false;
   if (o->rotations != 0 && o->rotations != 1) return false;
   if (o->share_min_far < -1) return false;
+  if (o->cols_per_block != 0 && o->cols_per_block != 32 && o->cols_per_block != 64) return false;
+  if (o->cols_per_block == 32 && !(o->rotations == 1 && o->precision == 0)) return false;
   return true;
 }
 
-// tile size: explicit option, else the autotuner's choice for this problem
-// set, else a size rule
-int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
-  if (o && (o->nb == 64 || o->nb == 128)) return o->nb;
+// tile size and far-block width: explicit options, else the autotuner's
+// choice for this problem set, else a size rule (and 64 columns)
+struct Tile {
+  int nb, fcb;
+};
+bool l3_form(const hsrq_opts_t* o) { return o && o->rotations == 1 && o->precision == 0; }
+Tile choose_tile(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
+  Tile t{heuristic_nb(count, probs), 64};
   if (h && !h->tuned.empty()) {
     const uint64_t key = problem_signature(count, probs);
     for (auto& e : h->tuned)
-      if (e.first == key) return e.second;
+      if (e.key == key) t = Tile{e.nb, e.fcb};
   }
-  return heuristic_nb(count, probs);
+  if (o && (o->nb == 64 || o->nb == 128)) t.nb = o->nb;
+  if (o && (o->cols_per_block == 32 || o->cols_per_block == 64)) t.fcb = o->cols_per_block;
+  if (!l3_form(o)) t.fcb = 64;  // the one-at-a-time and FP32 far kernels take 64 columns
+  return t;
+}
+int choose_nb(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
+  return choose_tile(h, count, probs, o).nb;
 }
 
 // pinned staging buffer created with the handle (grown by later calls that
@@ -477,7 +495,10 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
   }
   { ProfScope ps(h, HSRQ_K_INIT, s); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
   // steps: critical tasks on s, far tasks on the second stream; step t of
-  // either kind waits for both kinds of step t-1
+  // either kind waits for both kinds of step t-1.  (Letting the next
+  // critical step start once only the far tile row next to the diagonal is
+  // done was measured slower: the rest of the far tiles then hold the compute
+  // units that the critical blocks, with their 96 KB of shared memory, need.)
   const int T = (int)P.coff.size();
   hipStream_t a = h->aux;
   hipEvent_t ev_fork = h->sync_ev[0], ev_crit = h->sync_ev[1], ev_far = h->sync_ev[2];
@@ -495,7 +516,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
       ProfScope ps(h, HSRQ_K_FAR, a, true);
-      launch_far(P.nb, P.prec, P.l3rot, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
+      launch_far(P.nb, P.prec, P.l3rot, P.fcb, dd, dt + P.foff[t], P.fcnt[t], a, ps.a, ps.b);
     }
     hipEventRecord(ev_crit, s);
     hipEventRecord(ev_far, a);
@@ -530,6 +551,7 @@ uint64_t plan_signature(const Plan& P, int count, void* work, bool want_res) {
   g.add((uint64_t)P.nb);
   g.add((uint64_t)(P.prec * 2 + P.l3rot));
   g.add((uint64_t)(uint32_t)P.share);
+  g.add((uint64_t)P.fcb);
   g.add((uint64_t)count);
   g.add((uint64_t)reinterpret_cast<uintptr_t>(work));
   g.add((uint64_t)want_res);
@@ -858,7 +880,8 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
         const hsrq_opts_t* o, bool batched) {
   if (o && o->precision == 1) return run_mixed(h, count, probs, work, work_bytes, o);
   Plan P;
-  build_plan(P, count, probs, choose_nb(h, count, probs, o));
+  const Tile tl = choose_tile(h, count, probs, o);
+  build_plan(P, count, probs, tl.nb, tl.fcb);
   P.l3rot = o ? o->rotations : 0;
   P.share = share_min(o);
   if (!work || work_bytes < P.total_bytes || (reinterpret_cast<uintptr_t>(work) & (kAlign - 1)))
@@ -880,6 +903,7 @@ int run(hsrq_handle_t h, int count, const hsrq_problem_t* probs, void* work, siz
 namespace hsrq {
 
 int handle_device(hsrq_handle_t h) { return h->device; }
+hipStream_t handle_stream(hsrq_handle_t h) { return h->stream; }
 bool opts_valid(const hsrq_opts_t* o) { return opts_ok(o); }
 
 // The single-problem solve (precision 0) in the given workspace with nothing
@@ -888,7 +912,8 @@ bool opts_valid(const hsrq_opts_t* o) { return opts_ok(o); }
 // (created with the handle), no graph, no profiling events.
 int run_noalloc(hsrq_handle_t h, const hsrq_problem_t& p, void* work, size_t work_bytes, const hsrq_opts_t* o) {
   Plan P;
-  build_plan(P, 1, &p, choose_nb(h, 1, &p, o));
+  const Tile tl = choose_tile(h, 1, &p, o);
+  build_plan(P, 1, &p, tl.nb, tl.fcb);
   P.l3rot = o ? o->rotations : 0;
   P.share = share_min(o);
   if (work_bytes < P.total_bytes || P.head_bytes > h->staging_bytes) return HSRQ_ERR_TOO_LARGE;
@@ -913,9 +938,12 @@ size_t plan_bytes(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const
   const bool mixed = o && o->precision == 1;
   for (int nb : kNbCandidates) {
     if (o && (o->nb == 64 || o->nb == 128) && nb != o->nb) continue;
-    Plan P;
-    build_plan(P, count, probs, nb);
-    b = std::max(b, mixed ? mixed_layout(count, probs, P.total_bytes).total : P.total_bytes);
+    for (int fcb : {32, 64}) {  // the task lists of 32-column far blocks are longer
+      if (fcb == 32 && !l3_form(o)) continue;
+      Plan P;
+      build_plan(P, count, probs, nb, fcb);
+      b = std::max(b, mixed ? mixed_layout(count, probs, P.total_bytes).total : P.total_bytes);
+    }
   }
   (void)h;
   return b;
@@ -1253,7 +1281,7 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
 }
 
 int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, void* work, size_t work_bytes,
-                  const hsrq_opts_t* opts, int* best_nb, double* ms) {
+                  const hsrq_opts_t* opts, int* best_nb, int* best_cb, double* ms) {
   if (!h || count < 1 || !problems || !best_nb || !work || !opts_ok(opts)) return HSRQ_ERR_ARG;
   for (int p = 0; p < count; ++p)
     if (check_problem(problems[p])) return HSRQ_ERR_ARG;
@@ -1264,14 +1292,17 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
   hipStream_t s = h->stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return HSRQ_ERR_HIP;
-  int best = 0;
+  Tile best{0, 0};
   double best_ms = 0.0;
   int st = HSRQ_OK;
-  for (int c = 0; c < 2 && st == HSRQ_OK; ++c) {
-    const int nb = kNbCandidates[c];
+  // the grid: tile sizes x far-block widths (32 only for the level-3 form);
+  // ms[2 * (nb == 128) + (fcb == 64)]
+  for (int c = 0; c < 4 && st == HSRQ_OK; ++c) {
+    const int nb = kNbCandidates[c / 2], fcb = (c & 1) ? 64 : 32;
     if (ms) ms[c] = 0.0;
+    if (fcb == 32 && !l3_form(&o)) continue;
     Plan P;
-    build_plan(P, count, problems, nb);
+    build_plan(P, count, problems, nb, fcb);
     P.prec = o.precision == 1 ? 1 : 0;
     P.l3rot = o.rotations;
     P.share = share_min(&o);
@@ -1291,24 +1322,26 @@ int hsrq_autotune(hsrq_handle_t h, int count, const hsrq_problem_t* problems, vo
     }
     if (st) break;
     if (ms) ms[c] = t_best;
-    if (best == 0 || t_best < best_ms) {
-      best = nb;
+    if (best.nb == 0 || t_best < best_ms) {
+      best = Tile{nb, fcb};
       best_ms = t_best;
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st) return st;
-  if (best == 0) return HSRQ_ERR_WORKSPACE;
+  if (best.nb == 0) return HSRQ_ERR_WORKSPACE;
   const uint64_t key = problem_signature(count, problems);
   bool found = false;
   for (auto& e : h->tuned)
-    if (e.first == key) {
-      e.second = best;
+    if (e.key == key) {
+      e.nb = best.nb;
+      e.fcb = best.fcb;
       found = true;
     }
-  if (!found) h->tuned.emplace_back(key, best);
-  *best_nb = best;
+  if (!found) h->tuned.push_back(hsrq_handle_s::Tuned{key, best.nb, best.fcb});
+  *best_nb = best.nb;
+  if (best_cb) *best_cb = best.fcb;
   return HSRQ_OK;
 }
 
@@ -1320,7 +1353,8 @@ int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_
   hsrq_problem_t p{};
   p.n = n; p.m = m; p.wr = wr.data(); p.wi = wi;
   Plan P;
-  build_plan(P, 1, &p, choose_nb(h, 1, &p, opts));
+  const Tile tl = choose_tile(h, 1, &p, opts);
+  build_plan(P, 1, &p, tl.nb, tl.fcb);
   const ProbPlan& q = P.pp[0];
   if (C) *C = at<double>(work, q.o_C);
   if (S) *S = at<double>(work, q.o_S);
@@ -1335,15 +1369,16 @@ int hsrq_debug_view(hsrq_handle_t h, int n, int m, const double* wi, const hsrq_
   return HSRQ_OK;
 }
 
-// Tuner cache: one line per problem-set signature, "<signature hex> <nb>",
-// after a header line; entries loaded are merged into the handle's (a loaded
-// entry replaces one with the same signature).
+// Tuner cache: one line per problem-set signature, "<signature hex> <nb>
+// <far-block width>", after a header line; entries loaded are merged into
+// the handle's (a loaded entry replaces one with the same signature).
 int hsrq_autotune_save(hsrq_handle_t h, const char* path) {
   if (!h || !path) return HSRQ_ERR_ARG;
   FILE* f = std::fopen(path, "w");
   if (!f) return HSRQ_ERR_ARG;
-  bool ok = std::fprintf(f, "hsrq-tuner 1\n") > 0;
-  for (auto& e : h->tuned) ok = ok && std::fprintf(f, "%016llx %d\n", (unsigned long long)e.first, e.second) > 0;
+  bool ok = std::fprintf(f, "hsrq-tuner 2\n") > 0;
+  for (auto& e : h->tuned)
+    ok = ok && std::fprintf(f, "%016llx %d %d\n", (unsigned long long)e.key, e.nb, e.fcb) > 0;
   ok = (std::fclose(f) == 0) && ok;
   return ok ? HSRQ_OK : HSRQ_ERR_ARG;
 }
@@ -1354,26 +1389,26 @@ int hsrq_autotune_load(hsrq_handle_t h, const char* path) {
   if (!f) return HSRQ_ERR_ARG;
   char head[32] = {0};
   int st = HSRQ_OK;
-  if (!std::fgets(head, sizeof head, f) || std::strncmp(head, "hsrq-tuner 1", 12) != 0) st = HSRQ_ERR_ARG;
-  std::vector<std::pair<uint64_t, int>> got;
+  if (!std::fgets(head, sizeof head, f) || std::strncmp(head, "hsrq-tuner 2", 12) != 0) st = HSRQ_ERR_ARG;
+  std::vector<hsrq_handle_s::Tuned> got;
   unsigned long long key = 0;
-  int nb = 0;
+  int nb = 0, fcb = 0;
   while (st == HSRQ_OK) {
-    const int r = std::fscanf(f, "%llx %d", &key, &nb);
+    const int r = std::fscanf(f, "%llx %d %d", &key, &nb, &fcb);
     if (r == EOF) break;
-    if (r != 2 || (nb != 64 && nb != 128)) {
+    if (r != 3 || (nb != 64 && nb != 128) || (fcb != 32 && fcb != 64)) {
       st = HSRQ_ERR_ARG;
       break;
     }
-    got.emplace_back((uint64_t)key, nb);
+    got.push_back(hsrq_handle_s::Tuned{(uint64_t)key, nb, fcb});
   }
   std::fclose(f);
   if (st) return st;  // nothing merged from a malformed file
   for (auto& g : got) {
     bool found = false;
     for (auto& e : h->tuned)
-      if (e.first == g.first) {
-        e.second = g.second;
+      if (e.key == g.key) {
+        e = g;
         found = true;
       }
     if (!found) h->tuned.push_back(g);

@@ -31,8 +31,10 @@ void launch_crit(int nb, int prec, int l3rot, bool share, const ProbDesc* d, con
                  hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
 // applied as one product with the folded rotations W; else one at a time
-void launch_far(int nb, int prec, int l3rot, const ProbDesc* d, const Task* tasks, int ntasks, hipStream_t st,
-                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// fcb: columns per far-tile block of the level-3 form (32 or 64; the
+// one-at-a-time and FP32 forms always take 64)
+void launch_far(int nb, int prec, int l3rot, int fcb, const ProbDesc* d, const Task* tasks, int ntasks,
+                hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
@@ -52,16 +54,17 @@ struct Layout {
 constexpr int kCrit = 8;    // columns of a critical task
 
 struct ProbPlan {
-  int n, N, nb, ncols, ld, nblk;
+  int n, N, nb, ncols, ld, nblk, nfblk;
   Layout lay;
   // byte offsets inside the workspace
   size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
-  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z0, o_Z1, o_W0, o_W1, o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
+  size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z[2], o_W[2], o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
   size_t o_zero, o_HF, o_FLAG, o_HN, o_RPART, o_HFP, o_RNUMP;
 };
 
 struct Plan {
   int nb = 64;
+  int fcb = 64;    // columns per far-tile block (b_c of the far tasks)
   int prec = 0;    // 1: FP32 tile-update products
   int l3rot = 0;   // 1: off-diagonal rotations folded and applied on MFMA (opts.rotations)
   int share = kShareFar;  // far-tile blocks from which a step uses the CU-sharing critical kernel
@@ -82,7 +85,8 @@ struct Plan {
 Layout make_layout(int m, const double* wr, const double* wi);
 int count_cols(int m, const double* wi);
 // Carve the workspace and build every host-side table for tile size nb.
-void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb);
+// fcb: columns per far-tile block (64, or 32 for the level-3 form)
+void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb, int fcb = 64);
 // Writes the plan's head region (descriptors, task and block tables, column
 // metadata) into the host image hb.
 void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* work, const hsrq_opts_t* o,
@@ -91,12 +95,13 @@ void fill_staging(const Plan& P, int count, const hsrq_problem_t* probs, void* w
 int check_problem(const hsrq_problem_t& p);
 // options outside their documented values
 bool opts_valid(const hsrq_opts_t* o);
+
 // scratch for hsrq_dhsrq3_noalloc (hsrq_noalloc.hip): scratch_init records
 // the address of the device's copy (once per device, with it current)
 int scratch_init(int device);
 int handle_device(hsrq_handle_t h);
+hipStream_t handle_stream(hsrq_handle_t h);
 int run_noalloc(hsrq_handle_t h, const hsrq_problem_t& p, void* work, size_t work_bytes, const hsrq_opts_t* o);
-
 
 template <class T>
 T* at(void* base, size_t off) {

@@ -124,6 +124,7 @@ struct hsrq_server_s {
   size_t budget = 0, used = 0;
   hsrq_opts_t opts{};
   int nb = 128;
+  int fcb = 64;  // columns per far-tile block of the all-FP64 requests
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -162,9 +163,9 @@ hipEvent_t get_event(hsrq_server_s* S) {
 
 // workspace of one request: the plan, then (precision 1) the kept starting
 // vectors and an internal residual array
-size_t request_bytes(const hsrq_problem_t& p, int prec, int nb, size_t* plan_bytes, size_t* keep_off) {
+size_t request_bytes(const hsrq_problem_t& p, int prec, int nb, int fcb, size_t* plan_bytes, size_t* keep_off) {
   Plan P;
-  build_plan(P, 1, &p, nb);
+  build_plan(P, 1, &p, nb, prec == 0 ? fcb : 64);
   size_t w = align_up(P.total_bytes);
   *keep_off = w;
   const size_t cols = (size_t)count_cols(p.m, p.wi);
@@ -176,7 +177,7 @@ size_t request_bytes(const hsrq_problem_t& p, int prec, int nb, size_t* plan_byt
 // admission: workspace, plan, head image; enqueue head copy, prep, init
 int admit(hsrq_server_s* S, Req* r) {
   size_t pb = 0, keep = 0;
-  const size_t wb = request_bytes(r->prob, r->prec, S->nb, &pb, &keep);
+  const size_t wb = request_bytes(r->prob, r->prec, S->nb, S->fcb, &pb, &keep);
   r->work = S->dpool.get(wb, &r->work_cap);
   if (!r->work) return HSRQ_ERR_ALLOC;
   r->o_keep = keep;
@@ -184,7 +185,7 @@ int admit(hsrq_server_s* S, Req* r) {
     const size_t cols = (size_t)count_cols(r->prob.m, r->prob.wi);
     r->prob.resid = at<double>(r->work, keep + align_up(sizeof(double) * (size_t)r->prob.n * cols));
   }
-  build_plan(r->plan, 1, &r->prob, S->nb);
+  build_plan(r->plan, 1, &r->prob, S->nb, r->prec == 0 ? S->fcb : 64);
   r->plan.prec = r->prec;
   r->head = S->hpool.get(r->plan.head_bytes, &r->head_cap);
   if (!r->head) return HSRQ_ERR_ALLOC;
@@ -261,7 +262,7 @@ int tick(hsrq_server_s* S) {
                                      : Task{p, task_code(TK_CRIT, t), d.N - t - 1, L});
     if (t > 0)
       for (int i = 0; i < d.N - t - 1; ++i)
-        for (int L = 0; L < d.nblk; ++L) far[r->prec].push_back(Task{p, task_code(TK_FAR, t), i, L});
+        for (int L = 0; L < d.nfblk; ++L) far[r->prec].push_back(Task{p, task_code(TK_FAR, t), i, L});
   }
   const size_t bd = align_up(sizeof(ProbDesc) * descs.size());
   size_t off[4], tot = bd;
@@ -291,7 +292,8 @@ int tick(hsrq_server_s* S) {
     if (!crit[pr].empty())
       launch_crit(S->nb, pr, S->opts.rotations, (int)far[pr].size() >= share_min(&S->opts), dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
-      launch_far(S->nb, pr, S->opts.rotations, dd, reinterpret_cast<const Task*>(db + off[2 + pr]), (int)far[pr].size(), a);
+      launch_far(S->nb, pr, S->opts.rotations, pr == 0 ? S->fcb : 64, dd, reinterpret_cast<const Task*>(db + off[2 + pr]),
+                 (int)far[pr].size(), a);
   }
   hipEventRecord(S->ev_far, a);
   // advance; requests whose last step ran get their final kernels
@@ -361,7 +363,7 @@ int check_request(hsrq_server_s* S, Req* r) {
   q.ldx = pr.n;
   c->prob = q;
   size_t pb = 0, keep = 0;
-  const size_t wb = request_bytes(q, 0, S->nb, &pb, &keep);
+  const size_t wb = request_bytes(q, 0, S->nb, S->fcb, &pb, &keep);
   const size_t nc = c->child_cols.size();
   const size_t tail = align_up(sizeof(double) * pr.n * nc) + align_up(24 * (size_t)q.m + 64);
   c->work = S->dpool.get(wb + tail, &c->work_cap);
@@ -382,7 +384,7 @@ int check_request(hsrq_server_s* S, Req* r) {
   // admit the child with its preallocated workspace
   void* w = c->work;
   size_t wc = c->work_cap;
-  build_plan(c->plan, 1, &c->prob, S->nb);
+  build_plan(c->plan, 1, &c->prob, S->nb, S->fcb);
   c->plan.prec = 0;
   c->head = S->hpool.get(c->plan.head_bytes, &c->head_cap);
   if (!c->head) return HSRQ_ERR_ALLOC;
@@ -481,10 +483,11 @@ int progress(hsrq_server_s* S) {
   return HSRQ_OK;
 }
 
-int tick_bytes_estimate(const Req* r, int nb) {
+int tick_bytes_estimate(const Req* r, int nb, int fcb) {
   const int N = (r->prob.n + nb - 1) / nb;
   const int cols = count_cols(r->prob.m, r->prob.wi);
-  const int nblk = (cols + kCB - 1) / kCB, ncrit = (cols + kCrit - 1) / kCrit;
+  const int f = r->prec == 0 ? fcb : 64;
+  const int nblk = (cols + f - 1) / f, ncrit = (cols + kCrit - 1) / kCrit;
   return (int)(sizeof(ProbDesc) + sizeof(Task) * ((size_t)ncrit + (size_t)std::max(N - 2, 0) * nblk) + 512);
 }
 
@@ -515,10 +518,10 @@ void worker_main(hsrq_server_s* S) {
     {
       std::unique_lock<std::mutex> g(S->mu);
       int tick_est = 0;
-      for (auto& r : S->live) tick_est += tick_bytes_estimate(r.get(), S->nb);
+      for (auto& r : S->live) tick_est += tick_bytes_estimate(r.get(), S->nb, S->fcb);
       while (!S->queue.empty()) {
         Req* r = S->queue.front().get();
-        const int tb = tick_bytes_estimate(r, S->nb);
+        const int tb = tick_bytes_estimate(r, S->nb, S->fcb);
         if (S->used + r->charge > S->budget || tick_est + tb > (int)(kTickBytes / kRing) / 2) break;
         S->used += r->charge;
         tick_est += tb;
@@ -588,12 +591,14 @@ int hsrq_server_create(hsrq_server_t* out, int device, size_t hbm_budget_bytes, 
   if (opts && opts->nb != 0 && opts->nb != 64 && opts->nb != 128) return -4;
   if (opts && opts->precision != 0 && opts->precision != 1) return -4;
   if (opts && opts->rotations != 0 && opts->rotations != 1) return -4;
+  if (opts && !opts_valid(opts)) return -4;
   hsrq_server_s* S = new (std::nothrow) hsrq_server_s();
   if (!S) return HSRQ_ERR_ALLOC;
   S->device = device;
   S->budget = hbm_budget_bytes;
   if (opts) S->opts = *opts;
   S->nb = (opts && opts->nb) ? opts->nb : 128;
+  S->fcb = (opts && opts->cols_per_block == 32 && opts->rotations == 1) ? 32 : 64;
   S->t0 = std::chrono::steady_clock::now();
   S->worker = std::thread(worker_main, S);
   std::unique_lock<std::mutex> g(S->mu);
@@ -623,11 +628,11 @@ int hsrq_server_submit(hsrq_server_t S, const hsrq_problem_t* problem, uint64_t 
   r->prec = S->opts.precision;
   size_t pb = 0, keep = 0;
   const size_t cols = (size_t)count_cols(problem->m, problem->wi);
-  r->charge = size_class(request_bytes(r->prob, r->prec, S->nb, &pb, &keep)) +
+  r->charge = size_class(request_bytes(r->prob, r->prec, S->nb, S->fcb, &pb, &keep)) +
               sizeof(double) * (size_t)problem->ldh * problem->n + sizeof(double) * (size_t)problem->ldx * cols;
   if (r->prec == 1) r->charge += r->charge / 2;  // room for a fallback child
   if (r->charge > S->budget) return HSRQ_ERR_BUSY;
-  if (tick_bytes_estimate(r.get(), S->nb) > (int)(kTickBytes / kRing) / 2) return HSRQ_ERR_BUSY;
+  if (tick_bytes_estimate(r.get(), S->nb, S->fcb) > (int)(kTickBytes / kRing) / 2) return HSRQ_ERR_BUSY;
   {
     // order the request after the work the caller has enqueued on its
     // stream so far (NULL is the null stream, torch's default stream; the

@@ -1,6 +1,6 @@
 """Comparison helpers for the GPU-vs-reference parity tests.
 
-Tolerances (the benchmark spec of the project, restated):
+Tolerances (the accuracy targets of the solver, restated):
   * normalised residual ||H y - lambda y|| / (||H||_F ||y||) <= 10 n eps64
     for eigenvalue shifts;
   * direction agreement |y^H y_ref| / (||y|| ||y_ref||) >= 1 - 1e-10 for

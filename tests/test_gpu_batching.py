@@ -100,16 +100,48 @@ def test_autotune_leaves_inputs_and_is_used(solver):
     probs = to_dev(hs)
     before = [host(p["X"]) for p in probs]
     print("[gpu] autotune: 12 problems", flush=True)
-    best, ms = solver.autotune(probs)
+    best, best_cb, ms = solver.autotune(probs)
     torch.cuda.synchronize()
-    assert best in (64, 128)
-    assert all(v > 0 for v in ms.values())
+    assert best in (64, 128) and best_cb == 64  # one-at-a-time form: 64 columns
+    assert all(ms[(nb, 64)] > 0 and ms[(nb, 32)] == 0 for nb in (64, 128))
     for p, b in zip(probs, before):
         assert np.array_equal(host(p["X"]), b)
     got = results(probs, solver.batched(probs))
     for (H, wr, wi, B), (Yg, Eg, mg, ig) in zip(hs, got):
         Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
         compare(Yg, Eg, mg, ig, Yo, Eo, muo, infoo, wi, dir_tol=1e-9)
+
+
+def test_autotune_grid_level3_and_block_widths(solver):
+    """Level-3 form: the tuner times the four (tile size, far-block width)
+    pairs; every width gives the same bits (a column's arithmetic does not
+    depend on which block carries it) and the tuned pair is what nb = 0,
+    cols_per_block = 0 then use."""
+    hs = uneven_set(14, 10, 700)
+    probs = to_dev(hs)
+    print("[gpu] autotune grid, level-3 form: 10 problems", flush=True)
+    best, best_cb, ms = solver.autotune(probs, rotations=1)
+    print(f"[gpu] grid {ms}, best ({best}, {best_cb})", flush=True)
+    assert best in (64, 128) and best_cb in (32, 64)
+    assert all(v > 0 for v in ms.values())
+    outs = {}
+    for cb in (32, 64):
+        pr = to_dev(hs)
+        outs[cb] = results(pr, solver.batched(pr, nb=best, rotations=1, cols_per_block=cb))
+    for a, b in zip(outs[32], outs[64]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    pr = to_dev(hs)
+    tuned = results(pr, solver.batched(pr, rotations=1))
+    for a, b in zip(tuned, outs[best_cb]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    # (the level-3 form against the reference is tested in test_gpu_level3.py;
+    # it agrees to the first-order bound, not bit for bit)
+    for (H, wr, wi, B), (Yg, Eg, mg, ig) in zip(hs, outs[32]):
+        conv = ig == 0
+        res = O.residual(H, wr, wi, Yg)
+        assert np.all(res[conv] <= 10 * H.shape[0] * 2.0 ** -52), res[conv].max()
 
 
 def test_c4_batched_sampled(solver):
@@ -159,7 +191,7 @@ def test_tuner_cache_round_trip(solver, tmp_path):
     wr, wi = np.linspace(-1.0, 1.0, 20), np.zeros(20)
     B = np.ones((n, 20))
     s1 = Solver(0)  # a handle of its own: one tuned entry
-    best, ms = s1.autotune([dict(H=dev(H), wr=wr, wi=wi, X=dev(B))])
+    best, _, ms = s1.autotune([dict(H=dev(H), wr=wr, wi=wi, X=dev(B))])
     print(f"[gpu] tuner: best nb {best}, ms {ms}", flush=True)
     path = str(tmp_path / "tuner.txt")
     s1.autotune_save(path)
@@ -174,9 +206,9 @@ def test_tuner_cache_round_trip(solver, tmp_path):
     # is what the planner uses, whichever size the timing picked
     other = 64 if best == 128 else 128
     lines = open(path).read().splitlines()
-    assert lines[0] == "hsrq-tuner 1" and len(lines) == 2
-    key, _ = lines[1].split()
-    open(path, "w").write(f"hsrq-tuner 1\n{key} {other}\n")
+    assert lines[0] == "hsrq-tuner 2" and len(lines) == 2
+    key, _, cb = lines[1].split()
+    open(path, "w").write(f"hsrq-tuner 2\n{key} {other} {cb}\n")
     s2.autotune_load(path)
     assert s2.debug_view(n, wi)["nb"] == other
     bad = str(tmp_path / "bad.txt")

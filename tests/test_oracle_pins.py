@@ -524,3 +524,49 @@ def test_restart_constant_row_sums():
         assert direction(y, V[:, idx]) > 1.0 - 1e-10
         r = O.solve1(H, complex(wr[k], wi[k]), S[:, 1].astype(complex) if wi[k] else S[:, 1])
         assert np.array_equal(y, r["y"]) and E[k] == r["E"] and mu[k] == r["mu"]
+
+
+# ---------------------------------------------------------------------------
+# the steps around the solve (Sec. 1): Hessenberg reduction and back-transform
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 60, 150])
+def test_hessenberg_reduction_against_lapack(n):
+    """The reference's reduction against scipy's (LAPACK DGEHRD, the same
+    reflector convention): the same H and Q0 to rounding; Q0 orthogonal,
+    Q0^T A Q0 = H, H upper Hessenberg, and the eigenvalues kept."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(300 + n)
+    A = rng.standard_normal((n, n))
+    R, tau = O.hessenberg_reduce(A)
+    H = O.hessenberg_part(R)
+    Q = O.apply_q(R, tau, np.eye(n))
+    Hs, Qs = sl.hessenberg(A, calc_q=True)
+    tol = 50 * n * EPS * max(1.0, np.linalg.norm(A))
+    assert np.max(np.abs(H - Hs)) <= tol
+    assert np.max(np.abs(Q - Qs)) <= 50 * n * EPS
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 10 * n * EPS
+    assert np.max(np.abs(Q.T @ A @ Q - H)) <= tol
+    assert np.all(np.tril(H, -2) == 0.0)
+    if n > 2:
+        assert tau[n - 2] == 0.0
+
+
+def test_back_transform_gives_eigenvectors_of_a():
+    """Eigenvectors of H mapped by Q0 are eigenvectors of A (z = Q0 x, Sec. 1):
+    the reference's solve on H, then apply_q, against numpy's eigenvectors of
+    A for well-separated real eigenvalues."""
+    rng = np.random.default_rng(5)
+    n = 40
+    A = rng.standard_normal((n, n))
+    R, tau = O.hessenberg_reduce(A)
+    H = O.hessenberg_part(R)
+    w, V = np.linalg.eig(A)
+    real = [k for k in range(n) if abs(w[k].imag) < 1e-12
+            and np.min(np.abs(np.delete(w, k) - w[k])) > 1e-2 * np.abs(w).max()][:4]
+    assert real
+    for k in real:
+        r = O.solve1(H, w[k].real, np.ones(n))
+        z = O.apply_q(R, tau, r["y"][:, None])[:, 0]
+        assert direction(z, V[:, k].real) > 1.0 - 1e-10
+        res = np.linalg.norm(A @ z - w[k].real * z) / (np.linalg.norm(A) * np.linalg.norm(z))
+        assert res <= 10 * n * EPS
