@@ -139,6 +139,28 @@ def colmajor(t):
     return tc, max(1, r)
 
 
+class Batch:
+    """A problem set marshalled for hsrq_dhsrq3_batched (see Solver.prepare):
+    the descriptor array, the arrays it points to, and the per-problem output
+    views (E, mu, info, resid), which every call with this Batch overwrites."""
+
+    def __init__(self, arr, keep, outs, count, residual):
+        self.arr, self.keep, self.outs, self.count, self.residual = arr, keep, outs, count, residual
+        self.need = {}
+
+    def set_x(self, xs):
+        """New starting-vector arrays (same shapes and layout as before)."""
+        if len(xs) != self.count:
+            raise ValueError("one X per problem")
+        for p, X in enumerate(xs):
+            a = self.arr[p]
+            ld = X.stride(1) if X.shape[1] > 1 else a.n
+            if X.shape[0] != a.n or ld != a.ldx:
+                raise ValueError(f"X of problem {p} does not match the prepared layout")
+            a.X = X.data_ptr()
+        self.xs = list(xs)
+
+
 class Solver:
     """Handle + workspace management on one device, for torch tensors."""
 
@@ -298,46 +320,79 @@ class Solver:
         torch = self.torch
         count = len(problems)
         arr = (HsrqProblem * max(count, 1))()
-        keep, outs = [], []
+        keep = []
+        ms = [int(np.asarray(pr["wr"]).shape[0]) for pr in problems]
+        sizes = [max(m, 1) for m in ms]
+        tot = max(sum(sizes), 1)
+        dev = problems[0]["H"].device if count else torch.device("cuda", self.device)
+        # one allocation per output kind, split into per-problem views
+        E_all = torch.empty(tot, dtype=torch.int32, device=dev)
+        mu_all = torch.empty(tot, dtype=torch.float64, device=dev)
+        info_all = torch.empty(tot, dtype=torch.int32, device=dev)
+        res_all = torch.empty(tot, dtype=torch.float64, device=dev) if residual else None
+        keep += [E_all, mu_all, info_all, res_all]
+        Es = torch.split(E_all, sizes) if count else ()
+        mus = torch.split(mu_all, sizes) if count else ()
+        infos = torch.split(info_all, sizes) if count else ()
+        ress = torch.split(res_all, sizes) if (count and residual) else [None] * count
+        outs = []
+        off = 0
         for p, pr in enumerate(problems):
             Hc, ldh = colmajor(pr["H"])
             wr = np.ascontiguousarray(pr["wr"], dtype=np.float64)
             wi = np.ascontiguousarray(pr["wi"], dtype=np.float64)
             X = pr["X"]
-            m = wr.shape[0]
-            dev = Hc.device
-            E = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-            mu = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
-            info = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-            res = torch.empty(max(m, 1), dtype=torch.float64, device=dev) if residual else None
+            m = ms[p]
             keep += [Hc, wr, wi]
-            outs.append((E[:m], mu[:m], info[:m], res[:m] if res is not None else None))
+            res = ress[p]
+            outs.append((Es[p][:m], mus[p][:m], infos[p][:m], res[:m] if res is not None else None))
             a = arr[p]
             a.n, a.H, a.ldh, a.m = Hc.shape[0], Hc.data_ptr(), ldh, m
             a.wr, a.wi = wr.ctypes.data, wi.ctypes.data
             a.X, a.ldx = X.data_ptr(), (X.stride(1) if X.shape[1] > 1 else Hc.shape[0])
-            a.scale_exp, a.scale_mant, a.info = E.data_ptr(), mu.data_ptr(), info.data_ptr()
-            a.resid = res.data_ptr() if res is not None else None
+            a.scale_exp = E_all.data_ptr() + 4 * off
+            a.scale_mant = mu_all.data_ptr() + 8 * off
+            a.info = info_all.data_ptr() + 4 * off
+            a.resid = res_all.data_ptr() + 8 * off if residual else None
+            off += sizes[p]
         return arr, keep, outs
+
+    def prepare(self, problems, residual=False):
+        """Marshals a problem set once (the C array of problem descriptors and
+        one output buffer per kind) for repeated calls of batched(): pass the
+        returned Batch in place of the list.  Its X pointers can be replaced
+        with Batch.set_x; every other input must stay where it is."""
+        arr, keep, outs = self._problem_array(problems, residual)
+        return Batch(arr, keep, outs, len(problems), residual)
 
     def batched(self, problems, nb=0, precision=0, residual=False, graph=0, stream=None, rotations=0,
                 share_min_far=0, cols_per_block=0):
         """problems: list of dict(H, wr, wi, X) with device H and X (column-major,
-        solved in place).  Returns a list of (E, mu, info, resid).  graph: 1
-        replay as a HIP graph, -1 launch kernel by kernel, 0 library default
-        (graph)."""
-        count = len(problems)
-        arr, keep, outs = self._problem_array(problems, residual)
+        solved in place), or a Batch from prepare().  Returns a list of (E, mu,
+        info, resid).  graph: 1 replay as a HIP graph, -1 launch kernel by
+        kernel, 0 library default (graph)."""
+        if isinstance(problems, Batch):
+            b = problems
+            if residual and not b.residual:
+                raise ValueError("this Batch was prepared without residual buffers")
+            residual = b.residual
+        else:
+            b = self.prepare(problems, residual)
+        count, arr = b.count, b.arr
         o = _opts(nb, precision, residual, graph, rotations, share_min_far, cols_per_block)
-        need = ctypes.c_size_t()
-        _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(need)),
-               "hsrq_workspace_size_batched")
-        wp, wb = self.workspace(need.value)
+        key = (nb, precision, residual, rotations, cols_per_block)
+        need = b.need.get(key)
+        if need is None:
+            nv = ctypes.c_size_t()
+            _check(self.lib.hsrq_workspace_size_batched(self.h, count, arr, ctypes.byref(o), ctypes.byref(nv)),
+                   "hsrq_workspace_size_batched")
+            need = b.need[key] = nv.value
+        wp, wb = self.workspace(need)
         self._stream(stream)
         _check(self.lib.hsrq_dhsrq3_batched(self.h, count, arr, ctypes.c_void_p(wp), wb, ctypes.byref(o)),
                "hsrq_dhsrq3_batched")
-        self._keep = keep
-        return outs
+        self._keep = b.keep
+        return b.outs
 
     def autotune(self, problems, precision=0, stream=None, rotations=0):
         """Times each (tile size, far-block width) on this problem set and

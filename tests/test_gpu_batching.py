@@ -217,3 +217,30 @@ def test_tuner_cache_round_trip(solver, tmp_path):
         s2.autotune_load(bad)
     assert s2.debug_view(n, wi)["nb"] == other
     s2.close()
+
+
+def test_prepared_batch_reuse(solver):
+    """A problem set marshalled once (Solver.prepare) and solved twice, the
+    second time with fresh starting vectors swapped in (Batch.set_x), gives
+    bit for bit the results of the unprepared call; a layout that does not
+    match is refused."""
+    hs = uneven_set(15, 20, 500)
+    print("[gpu] prepared batch: 20 problems", flush=True)
+    probs = to_dev(hs)
+    ref = results(probs, solver.batched(probs, nb=64, graph=1))
+    pr = to_dev(hs)
+    b = solver.prepare(pr)
+    for rep in range(2):
+        if rep:
+            xs = [dev(B) for _, _, _, B in hs]
+            b.set_x(xs)
+            for p, X in zip(pr, xs):
+                p["X"] = X
+        got = results(pr, solver.batched(b, nb=64, graph=1))
+        for r, g_ in zip(ref, got):
+            for x, y in zip(r, g_):
+                assert np.array_equal(x, y), rep
+    with pytest.raises(ValueError):
+        b.set_x([dev(B[:-1]) for _, _, _, B in hs])
+    with pytest.raises(ValueError):
+        solver.batched(b, residual=True)
