@@ -389,6 +389,77 @@ def bench_c4(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_hessenberg(args):
+    """The steps around the solve: Householder reduction of a general n x n
+    matrix to Hessenberg form (hsrq_gehrd) and the back-transform of ncols
+    vectors (hsrq_ormhr), on seeded standard-normal data.  One step = one
+    reduction plus one back-transform.  Both are HBM-bound: the algorithmic
+    bytes are one read and one write of the trailing matrix per reflector
+    (16 n (n - q - 2) for reflector q) and of the trailing rows of Z
+    (16 (n - q - 1) ncols)."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05063_amd import Solver
+
+    n, ncols = args.hess_n, args.hess_cols
+    rng = np.random.default_rng(2101)
+    dev = torch.device("cuda:0")
+    A0 = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((n, n)).T)).to(dev).t()
+    Z0 = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((n, ncols)).T)).to(dev).t()
+    solver = Solver(0)
+    K, W = args.steps, args.warmup
+    As = [A0.clone() for _ in range(K + W)]
+    Zs = [Z0.clone() for _ in range(K + W)]
+    torch.cuda.synchronize()
+    taus = [solver.gehrd(As[k]) for k in range(W)]
+    for k in range(W):
+        solver.ormhr(As[k], taus[k], Zs[k])
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t_red = t_bt = 0.0
+    for k in range(W, W + K):
+        e0.record()
+        tau = solver.gehrd(As[k])
+        e1.record()
+        solver.ormhr(As[k], tau, Zs[k])
+        e2.record()
+        torch.cuda.synchronize()
+        t_red += e0.elapsed_time(e1)
+        t_bt += e1.elapsed_time(e2)
+    ms_red, ms_bt = t_red / K, t_bt / K
+    bytes_red = sum(16.0 * n * (n - q - 2) for q in range(n - 2))
+    bytes_bt = sum(16.0 * (n - q - 1) * ncols for q in range(n - 2))
+    gbs_red = bytes_red / (ms_red * 1e-3) / 1e9
+    gbs_bt = bytes_bt / (ms_bt * 1e-3) / 1e9
+    # spot check of the last reduction: Q0 orthogonal on a few columns (Q0 e_j
+    # from the back-transform of unit vectors)
+    E = torch.zeros(n, 4, dtype=torch.float64, device=dev)
+    idx = [0, n // 3, n // 2, n - 1]
+    for j, i in enumerate(idx):
+        E[i, j] = 1.0
+    Q = solver.ormhr(As[-1], tau, E.t().contiguous().t())
+    orth = float((Q.t() @ Q - torch.eye(4, dtype=torch.float64, device=dev)).abs().max())
+    line = {
+        "metric": "Hessenberg reduction + back-transform time (n x n general matrix, ncols vectors)",
+        "value": round(ms_red + ms_bt, 3), "unit": "ms", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms_red + ms_bt, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"general standard-normal matrix n={n}, back-transform of {ncols} vectors",
+                   "n": n, "ncols": ncols},
+        "reduction": {"ms": round(ms_red, 3), "algorithmic_bytes": bytes_red, "achieved_GBps": round(gbs_red, 1),
+                      "frac_hbm_peak": round(gbs_red / PEAK_HBM_GBS, 4)},
+        "back_transform": {"ms": round(ms_bt, 3), "algorithmic_bytes": bytes_bt,
+                           "achieved_GBps": round(gbs_bt, 1), "frac_hbm_peak": round(gbs_bt / PEAK_HBM_GBS, 4)},
+        "roofline": {"kernel": "hsrq::k_sweep (reduction, whole call)", "bound": "hbm",
+                     "achieved": round(gbs_red, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs_red / PEAK_HBM_GBS, 4), "traffic": None},
+        "check": {"q0_orthogonality_4_columns": orth},
+    }
+    solver.close()
+    print(json.dumps(line), flush=True)
+
+
 def order_stat(x, q):
     """Exact order statistic: the smallest value with at least a fraction q of
     the sample at or below it."""
@@ -511,10 +582,12 @@ def main():
                          "1: folded into one matrix per tile column and applied on the matrix cores")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "c5", "hessenberg"], default="c3",
                     help="c3: the headline single-matrix solve; c4: 512 matrices of uneven order in one "
                          "graph launch (batching); c5: the serving loop under Poisson arrivals")
     ap.add_argument("--requests", type=int, default=2000, help="c5: open-loop arrivals")
+    ap.add_argument("--hess-n", type=int, default=8000, help="hessenberg: matrix order")
+    ap.add_argument("--hess-cols", type=int, default=1000, help="hessenberg: vectors back-transformed")
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="c3: Poisson arrivals of the serving sub-measurement (0 = skip it)")
     ap.add_argument("--one-form", action="store_true",
@@ -544,6 +617,9 @@ def main():
         return
     if args.workload == "c5":
         bench_c5(args)
+        return
+    if args.workload == "hessenberg":
+        bench_hessenberg(args)
         return
 
     import numpy as np

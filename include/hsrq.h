@@ -265,9 +265,10 @@ int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
  * eigenvector z = Q0 x of A.  Q0 = H_0 H_1 ... H_{n-3}, H_k = I - tau_k u_k
  * u_k^T, u_k zero above row k+1, u_k(k+1) = 1; the layout is LAPACK's DGEHRD
  * one, with H_k A(k+1:n, k) = beta e_1 and beta = -sign(A(k+1, k)) times the
- * norm of A(k+1:n, k).  Unblocked (one reflector at a time, each applied
- * with matrix-vector and rank-1 kernels), asynchronous on the handle's
- * stream, workspace from the caller (256-byte aligned).
+ * norm of A(k+1:n, k).  Unblocked (one reflector at a time; each step is
+ * one read and one write of the trailing matrix, which also forms the
+ * products the next reflector needs), asynchronous on the handle's stream,
+ * workspace from the caller (256-byte aligned).  Run-to-run deterministic.
  *
  * hsrq_gehrd: A (device, n x n, lda >= n) in: general; out: H on and above
  *   the first subdiagonal, u_k(k+2:n) below it in column k.  tau (device,

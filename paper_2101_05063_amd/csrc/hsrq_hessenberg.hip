@@ -8,18 +8,21 @@
 // chosen so that H_k A(k+1:n, k) = beta e_1 with beta = -sign(alpha) ||x||,
 // alpha = A(k+1, k) (no cancellation in alpha - beta).
 //
-// One Householder step per column, on the device:
-//   k_house        the reflector of column k (one block; norms by a scaled
-//                  sum of squares reduced in a fixed order)
-//   k_gemv_rows    y = A(:, k+1:n) u, partial sums per column chunk, and
-//   k_sum_chunks   their sum in chunk order
-//   k_rank1        A(r0:, c0:) -= tau y u^T (from the right) or
-//                  tau u w^T (from the left), 64 x 64 tiles
-//   k_dot_cols     w = u^T A(k+1:n, k+1:n): one wave per column
-// (right application first, then left, as LAPACK's DGEHD2).  The
-// back-transform applies the reflectors in reverse order to the columns of
-// Z with k_dot_cols and k_rank1.  Every reduction has a fixed order, so the
-// results are the same on every run.
+// Applying H_k from both sides is one rank-2 update of the trailing columns:
+// with y = A(:, k+1:n) u and z = u^T A(k+1:n, k+1:n) (both from A before the
+// step) and s = u^T y(k+1:n),
+//   A(:, k+1:n)      -= tau y u^T                     (from the right)
+//   A(k+1:n, k+1:n)  -= tau u w^T,  w = z - tau s u   (then from the left).
+// The reduction is HBM-bound, so every column costs one read and one write of
+// the trailing matrix: the sweep that applies step k to columns k+2..n-1 also
+// forms the partial sums of y and z for step k+1 (whose reflector is known
+// once column k+1 alone has been updated).  Per column:
+//   k_reduce      y, z of step k from the partial sums (fixed order)
+//   k_colhouse    s; column k+1 updated; the reflector of column k+1
+//   k_sweep       columns k+2..n-1 updated; partial sums for step k+1
+// Every reduction has a fixed order, so the results are the same on every
+// run.  The back-transform applies the reflectors in reverse order to the
+// columns of Z with the same fusion (k_zsweep, k_reduce).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -29,7 +32,8 @@
 namespace hsrq {
 namespace {
 
-constexpr int kChunkCols = 256;  // columns per partial sum of k_gemv_rows
+constexpr int kT = 64;     // sweep tiles: 64 rows x 64 columns, 256 threads
+constexpr int kCH = 1024;  // threads of k_colhouse
 
 __device__ __forceinline__ double wsum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -39,185 +43,342 @@ __device__ __forceinline__ double wmax(double x) {
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
   return x;
 }
+// block sum / max over kCH threads in a fixed order (every thread gets it)
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  x = wsum(x);
+  __syncthreads();
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int j = 0; j < kCH / 64; ++j) t += red[j];
+  return t;
+}
+__device__ __forceinline__ double block_max(double x, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  x = wmax(x);
+  __syncthreads();
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int j = 0; j < kCH / 64; ++j) t = fmax(t, red[j]);
+  return t;
+}
 
-// Reflector of column k: x = A(k+1:n, k), m = n-k-1 entries.  Writes beta to
-// A(k+1, k), v = x(2:m) / (alpha - beta) in place, tau[k], and u = [1; v]
-// (length m) to the workspace.  One block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_house(double* A, long long lda, int n, int k, double* tau, double* u) {
-  const int m = n - k - 1;
-  double* x = A + (k + 1) + (long long)k * lda;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  __shared__ double red[16];
-  __shared__ double bc[3];
-  double mx = 0.0;
-  for (int i = 1 + tid; i < m; i += 1024) mx = fmax(mx, fabs(x[i]));
-  mx = wmax(mx);
-  if (lane == 0) red[w] = mx;
-  __syncthreads();
-  if (tid == 0) {
-    double v = 0.0;
-    for (int j = 0; j < 16; ++j) v = fmax(v, red[j]);
-    bc[0] = v;
+// One element of the rank-2 update of step k: tyr = tau y(r), tur = tau
+// u(r) (0 above row k+1), uc = u(c), wc = w(c).
+__device__ __forceinline__ double rank2(double a, double tyr, double uc, double tur, double wc) {
+  a = fma(-tyr, uc, a);
+  return fma(-tur, wc, a);
+}
+
+// Step q's s = u^T y(q+1:n), column q+1 updated with step q, and the
+// reflector of column q+1 (when q+1 <= n-3).  q = -1: only the reflector of
+// column 0.  One block of kCH threads; thread t owns rows t, t + kCH, ...
+// in both phases, so it reads back only what it wrote itself.
+__global__ void __launch_bounds__(kCH) k_colhouse(double* A, long long lda, int n, int q, double* tau,
+                                                  const double* uq, double* un, const double* y,
+                                                  const double* z, double* sc) {
+  __shared__ double red[kCH / 64];
+  __shared__ double alpha_s;
+  const int tid = threadIdx.x;
+  const int c = q + 1;  // the column updated here and reduced next
+  double* col = A + (long long)c * lda;
+  if (q >= 0) {
+    const int m = n - q - 1;
+    double sp = 0.0;
+    for (int i = tid; i < m; i += kCH) sp = fma(uq[i], y[q + 1 + i], sp);
+    const double s = block_sum(sp, red);
+    const double t = tau[q];
+    if (tid == 0) sc[0] = s;
+    const double w0 = fma(-(t * s), uq[0], z[0]);
+    for (int r = tid; r < n; r += kCH) {
+      const double tur = r >= q + 1 ? t * uq[r - (q + 1)] : 0.0;
+      col[r] = rank2(col[r], t * y[r], uq[0], tur, w0);
+    }
   }
-  __syncthreads();
-  mx = bc[0];
+  if (c > n - 3) return;  // no reflector for this column
+  // the reflector of column c: x = A(c+1:n, c), m entries
+  const int m = n - c - 1;
+  double* x = col + (c + 1);
+  if (tid == ((c + 1) % kCH)) alpha_s = col[c + 1];  // the thread that owns row c+1
+  double mx = 0.0;
+  for (int r = tid; r < n; r += kCH)
+    if (r >= c + 2) mx = fmax(mx, fabs(col[r]));
+  mx = block_max(mx, red);
   double ss = 0.0;
   if (mx > 0.0)
-    for (int i = 1 + tid; i < m; i += 1024) {
-      const double t = x[i] / mx;
-      ss = fma(t, t, ss);
+    for (int r = tid; r < n; r += kCH)
+      if (r >= c + 2) {
+        const double v = col[r] / mx;
+        ss = fma(v, v, ss);
+      }
+  ss = block_sum(ss, red);  // its first barrier also publishes alpha_s
+  const double xnorm = mx * sqrt(ss);
+  const double alpha = alpha_s;
+  double t = 0.0, beta = alpha, scal = 0.0;
+  if (xnorm != 0.0) {
+    // |beta| = hypot(alpha, xnorm), written out with a power-of-two scale
+    const double big = fmax(fabs(alpha), xnorm);
+    const int e = ilogb(big);
+    const double as = ldexp(alpha, -e), xs = ldexp(xnorm, -e);
+    const double r = ldexp(sqrt(fma(as, as, xs * xs)), e);
+    beta = alpha >= 0.0 ? -r : r;
+    t = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  for (int r = tid; r < n; r += kCH)
+    if (r >= c + 2) {
+      const double v = col[r] * scal;
+      col[r] = v;
+      un[r - (c + 1)] = v;
     }
-  ss = wsum(ss);
-  __syncthreads();
-  if (lane == 0) red[w] = ss;
-  __syncthreads();
   if (tid == 0) {
-    double s = 0.0;
-    for (int j = 0; j < 16; ++j) s += red[j];
-    const double xnorm = mx * sqrt(s);
-    const double alpha = x[0];
-    double t = 0.0, beta = alpha, scal = 0.0;
-    if (xnorm != 0.0) {
-      // |beta| = hypot(alpha, xnorm), written out with a power-of-two scale
-      const double big = fmax(fabs(alpha), xnorm);
-      const int e = ilogb(big);
-      const double as = ldexp(alpha, -e), xs = ldexp(xnorm, -e);
-      const double r = ldexp(sqrt(fma(as, as, xs * xs)), e);
-      beta = alpha >= 0.0 ? -r : r;
-      t = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
+    tau[c] = t;
+    x[0] = beta;
+    un[0] = 1.0;
+  }
+  (void)m;
+}
+
+// Column sums over the 64 rows of a tile for the CW = 16 columns of a wave:
+// each lane stores its row's products, then 4 lanes per column add 16 rows
+// each and combine the 4 sums, in a fixed order.  Returns the sum of column
+// (lane >> 2) in the lanes with (lane & 3) == 0.
+constexpr int kCW = 16;  // columns per wave in the sweeps
+__device__ __forceinline__ double tile_colsum(double (*zt)[kT + 1], const double* v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kCW; ++j) zt[j][l] = v[j];
+  __builtin_amdgcn_wave_barrier();
+  const int jj = l >> 2, pp = l & 3;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += zt[jj][pp * 16 + i];
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  __builtin_amdgcn_wave_barrier();  // zt is reused by the next call
+  return s;
+}
+
+// The sweep of step k over columns k+2..n-1 (all rows), 64 x 64 tiles: lane
+// = row, wave w = 16 columns.  UPD: apply step k (tau[k], u0 = u_k, y, z, s).
+// ACC: partial sums for step k+1 (u1 = u_{k+1}): py[ct][r] = sum over the
+// tile's columns of A(r, c) u1(c), pz[rt][c'] = sum over the tile's rows of
+// u1(r) A(r, c).  k = -1 with UPD false: the partial sums of step 0.  The
+// per-column values are wave-uniform; the 16 loads of a lane are issued
+// before any of them is used.
+template <bool UPD, bool ACC>
+__global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long lda, int n, int k,
+                                               const double* __restrict__ tau, const double* __restrict__ u0,
+                                               const double* __restrict__ u1, const double* __restrict__ y,
+                                               const double* __restrict__ z, const double* __restrict__ sc,
+                                               double* __restrict__ py, double* __restrict__ pz) {
+  __shared__ double red[4][kT];
+  __shared__ double zt[4][kCW][kT + 1];
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = blockIdx.x * kT + l;
+  const int c0 = k + 2;
+  const int cb = c0 + blockIdx.y * kT + w * kCW;
+  const bool rok = r < n;
+  const int rr = rok ? r : n - 1;
+  double tyr = 0.0, tur = 0.0, ts = 0.0, ur1 = 0.0;
+  if (UPD) {
+    const double t = tau[k];
+    ts = t * sc[0];
+    tyr = rok ? t * y[rr] : 0.0;
+    tur = (rok && r >= k + 1) ? t * u0[rr - (k + 1)] : 0.0;
+  }
+  if (ACC) ur1 = (rok && r >= k + 2) ? u1[rr - (k + 2)] : 0.0;
+  double a[kCW], uc[kCW], wc[kCW], vc[kCW];
+#pragma unroll
+  for (int j = 0; j < kCW; ++j) {
+    const int c = cb + j < n ? cb + j : n - 1;  // clamped: columns past n are never stored
+    a[j] = A[(long long)c * lda + rr];
+    if (UPD) {
+      uc[j] = u0[c - (k + 1)];
+      wc[j] = fma(-ts, uc[j], z[c - (k + 1)]);
     }
-    tau[k] = t;
-    bc[1] = beta;
-    bc[2] = scal;
+    if (ACC) vc[j] = u1[c - (k + 2)];
   }
-  __syncthreads();
-  const double scal = bc[2];
-  for (int i = 1 + tid; i < m; i += 1024) {
-    const double v = x[i] * scal;
-    x[i] = v;
-    u[i] = v;
-  }
-  if (tid == 0) {
-    x[0] = bc[1];
-    u[0] = 1.0;
-  }
-}
-
-// partial[chunk][r] = sum over the chunk's columns c of A(r, c0 + c) u[c],
-// rows r < nr; block = 64 rows x 4 column phases
-__global__ void __launch_bounds__(256) k_gemv_rows(const double* A, long long lda, int nr, int c0, int nc,
-                                                   const double* u, double* partial) {
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int r = blockIdx.x * 64 + tx;
-  const int ch = blockIdx.y;
-  const int cb = ch * kChunkCols, ce = min(nc, cb + kChunkCols);
-  __shared__ double red[4][64];
-  double s = 0.0;
-  if (r < nr)
-    for (int c = cb + ty; c < ce; c += 4) s = fma(A[r + (long long)(c0 + c) * lda], u[c], s);
-  red[ty][tx] = s;
-  __syncthreads();
-  if (ty == 0 && r < nr) partial[(long long)ch * nr + r] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
-}
-
-__global__ void __launch_bounds__(256) k_sum_chunks(const double* partial, int nr, int nch, double* y) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= nr) return;
-  double s = 0.0;
-  for (int ch = 0; ch < nch; ++ch) s += partial[(long long)ch * nr + r];
-  y[r] = s;
-}
-
-// w[c] = sum_r u[r] M(r0 + r, c0 + c), r < nr: one wave per column
-__global__ void __launch_bounds__(256) k_dot_cols(const double* M, long long ldm, int r0, int nr, int c0, int nc,
-                                                  const double* u, double* w) {
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (c >= nc) return;
-  const double* col = M + r0 + (long long)(c0 + c) * ldm;
-  double s = 0.0;
-  for (int r = lane; r < nr; r += 64) s = fma(u[r], col[r], s);
-  s = wsum(s);
-  if (lane == 0) w[c] = s;
-}
-
-// M(r0 + r, c0 + c) -= tau[k] a[r] b[c] over nr x nc, 64 x 64 tiles
-__global__ void __launch_bounds__(256) k_rank1(double* M, long long ldm, int r0, int nr, int c0, int nc,
-                                               const double* tau, int k, const double* a, const double* b) {
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int r = blockIdx.x * 64 + tx;
-  const double t = tau[k];
-  if (r >= nr || t == 0.0) return;
-  const double ar = t * a[r];
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int c = blockIdx.y * 64 + cc;
-    if (c < nc) {
-      double* p = M + r0 + r + (long long)(c0 + c) * ldm;
-      *p = fma(-ar, b[c], *p);
+  double ys = 0.0, zp[kCW];
+#pragma unroll
+  for (int j = 0; j < kCW; ++j) {
+    const int c = cb + j;
+    const bool cok = c < n;  // uniform over the wave
+    if (UPD) {
+      a[j] = rank2(a[j], tyr, uc[j], tur, wc[j]);
+      if (rok && cok) A[(long long)c * lda + r] = a[j];
+    }
+    const double uv = (rok && cok) ? a[j] : 0.0;
+    if (ACC) {
+      ys = fma(uv, vc[j], ys);
+      zp[j] = ur1 * uv;
     }
   }
+  if (ACC) {
+    const double zs = tile_colsum(zt[w], zp);
+    const int c = cb + (l >> 2);
+    if ((l & 3) == 0 && c < n) pz[(long long)blockIdx.x * n + (c - (k + 2))] = zs;
+    red[w][l] = ys;
+    __syncthreads();
+    if (w == 0 && rok) py[(long long)blockIdx.y * n + r] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+  }
 }
 
-// tau[n-2] = 0: the last reflector is the identity (LAPACK's convention)
+// y(i) = sum_ct py[ct][i] (i < ny; rows of py ny apart), z(c) = sum_rt
+// pz[rt][c] (c < m; rows of pz lz apart).  A block sums 64 outputs; its 4
+// waves each sum every 4th partial (in order) and the 4 sums are added in
+// a fixed order, so the result does not depend on the schedule.
+constexpr int kRO = 64;  // outputs per reduction block
+__global__ void __launch_bounds__(256) k_reduce(const double* py, int nct, int ny, const double* pz, int nrt,
+                                                long long lz, int m, double* y, double* z) {
+  __shared__ double part[4][kRO];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * kRO + o;
+  double s = 0.0;
+  if (i < ny) {
+#pragma unroll 8
+    for (int ct = g; ct < nct; ct += 4) s += py[(long long)ct * ny + i];
+  } else if (i < ny + m) {
+    const int c = i - ny;
+#pragma unroll 8
+    for (int rt = g; rt < nrt; rt += 4) s += pz[rt * lz + c];
+  }
+  part[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < ny + m) {
+    const double t = (part[0][o] + part[1][o]) + (part[2][o] + part[3][o]);
+    if (i < ny)
+      y[i] = t;
+    else
+      z[i - ny] = t;
+  }
+}
+
+// Back-transform sweep of reflector q over rows q..n-1 of Z (n x ncols),
+// 64 x 64 tiles.  UPD: rows q+1..n-1 -= tau[q] u_q(r) w(c).  ACC: partial
+// column sums of u_{q-1}(r) Z(r, c) over the tile's rows (row q included, it
+// is unchanged by step q) for the next reflector.  u_q(q+1) = 1 and
+// u_q(r) = A(r, q) below; q = n-2 with UPD false starts the recurrence.
+template <bool UPD, bool ACC>
+__global__ void __launch_bounds__(256) k_zsweep(const double* __restrict__ A, long long lda, int n, int q,
+                                                const double* __restrict__ tau, double* __restrict__ Z,
+                                                long long ldz, int ncols, const double* __restrict__ wv,
+                                                double* __restrict__ pw) {
+  __shared__ double zt[4][kCW][kT + 1];
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = q + blockIdx.x * kT + l;  // row tiles start at row q
+  const int cb = blockIdx.y * kT + w * kCW;
+  const bool rok = r < n;
+  const int rr = rok ? r : n - 1;
+  double tur = 0.0, un = 0.0;
+  if (UPD && rok && r >= q + 1) tur = tau[q] * (r == q + 1 ? 1.0 : A[rr + (long long)q * lda]);
+  if (ACC && rok) un = r == q ? 1.0 : A[rr + (long long)(q - 1) * lda];
+  double a[kCW], wj[kCW];
+#pragma unroll
+  for (int j = 0; j < kCW; ++j) {
+    const int c = cb + j < ncols ? cb + j : ncols - 1;
+    a[j] = Z[(long long)c * ldz + rr];
+    if (UPD) wj[j] = wv[c];
+  }
+  double zp[kCW];
+#pragma unroll
+  for (int j = 0; j < kCW; ++j) {
+    const int c = cb + j;
+    const bool cok = c < ncols;  // uniform over the wave
+    if (UPD) {
+      a[j] = fma(-tur, wj[j], a[j]);
+      if (rok && cok && r >= q + 1) Z[(long long)c * ldz + r] = a[j];
+    }
+    if (ACC) zp[j] = (rok && cok) ? un * a[j] : 0.0;
+  }
+  if (ACC) {
+    const double s = tile_colsum(zt[w], zp);
+    const int c = cb + (l >> 2);
+    if ((l & 3) == 0 && c < ncols) pw[(long long)blockIdx.x * ncols + c] = s;
+  }
+}
+
 __global__ void k_tau_tail(double* tau, int n) {
   if (threadIdx.x == 0) tau[n - 2] = 0.0;
 }
 
-// u = [1; A(k+2:n, k)] (the stored reflector of column k), m = n-k-1 entries
-__global__ void __launch_bounds__(256) k_make_u(const double* A, long long lda, int n, int k, double* u) {
-  const int i = blockIdx.x * 256 + threadIdx.x, m = n - k - 1;
-  if (i < m) u[i] = i == 0 ? 1.0 : A[(k + 1 + i) + (long long)k * lda];
-}
-
-dim3 tiles(int nr, int nc) { return dim3((nr + 63) / 64, (nc + 63) / 64); }
+int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace
 
-// workspace of the reduction: u (n), y (n), w (n), partial sums
+// workspace of the reduction: u (2 x n), y (n), z (n), s, and the partial
+// sums py, pz (each ceil(n / 64) x n)
 size_t gehrd_bytes(int n) {
-  const int nch = (n + kChunkCols - 1) / kChunkCols;
-  return align_up(sizeof(double) * (size_t)n) * 3 + align_up(sizeof(double) * (size_t)n * nch);
+  const size_t v = align_up(sizeof(double) * (size_t)n);
+  return 4 * v + align_up(sizeof(double) * 8) + 2 * align_up(sizeof(double) * (size_t)n * cdiv(n, kT));
 }
 
 int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
-  double* u = static_cast<double*>(work);
-  double* y = at<double>(work, align_up(sizeof(double) * (size_t)n));
-  double* w = at<double>(work, 2 * align_up(sizeof(double) * (size_t)n));
-  double* part = at<double>(work, 3 * align_up(sizeof(double) * (size_t)n));
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;  // rows and columns k+1 .. n-1
-    hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, st, A, (long long)lda, n, k, tau, u);
-    // from the right: A(0:n, k+1:n) -= tau (A(0:n, k+1:n) u) u^T
-    const int nch = (m + kChunkCols - 1) / kChunkCols;
-    hipLaunchKernelGGL(k_gemv_rows, dim3((n + 63) / 64, nch), dim3(256), 0, st, A, (long long)lda, n, k + 1, m, u,
-                       part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3((n + 255) / 256), dim3(256), 0, st, part, n, nch, y);
-    hipLaunchKernelGGL(k_rank1, tiles(n, m), dim3(256), 0, st, A, (long long)lda, 0, n, k + 1, m, tau, k, y, u);
-    // from the left: A(k+1:n, k+1:n) -= tau u (u^T A(k+1:n, k+1:n))
-    hipLaunchKernelGGL(k_dot_cols, dim3((m + 3) / 4), dim3(256), 0, st, A, (long long)lda, k + 1, m, k + 1, m, u, w);
-    hipLaunchKernelGGL(k_rank1, tiles(m, m), dim3(256), 0, st, A, (long long)lda, k + 1, m, k + 1, m, tau, k, u, w);
+  const size_t v = align_up(sizeof(double) * (size_t)n);
+  double* u[2] = {static_cast<double*>(work), at<double>(work, v)};
+  double* y = at<double>(work, 2 * v);
+  double* z = at<double>(work, 3 * v);
+  double* sc = at<double>(work, 4 * v);
+  double* py = at<double>(work, 4 * v + align_up(sizeof(double) * 8));
+  double* pz = py + (size_t)n * cdiv(n, kT);
+  const long long ld = lda;
+  const int nrt = cdiv(n, kT);
+  if (n >= 3) {
+    // the reflector of column 0 and the partial sums of step 0
+    hipLaunchKernelGGL(k_colhouse, dim3(1), dim3(kCH), 0, st, A, ld, n, -1, tau, u[1], u[0], y, z, sc);
+    hipLaunchKernelGGL((k_sweep<false, true>), dim3(nrt, cdiv(n - 1, kT)), dim3(256), 0, st, A, ld, n, -1, tau,
+                       u[1], u[0], y, z, sc, py, pz);
+    for (int q = 0; q <= n - 3; ++q) {
+      const int m = n - q - 1;  // rows and columns q+1 .. n-1
+      hipLaunchKernelGGL(k_reduce, dim3(cdiv(n + m, kRO)), dim3(256), 0, st, py, cdiv(m, kT), n, pz, nrt,
+                         (long long)n, m, y, z);
+      hipLaunchKernelGGL(k_colhouse, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, u[q & 1], u[(q + 1) & 1], y, z,
+                         sc);
+      const int nc = n - q - 2;  // columns q+2 .. n-1
+      if (nc > 0) {
+        const dim3 g(nrt, cdiv(nc, kT));
+        if (q + 1 <= n - 3)
+          hipLaunchKernelGGL((k_sweep<true, true>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
+                             u[(q + 1) & 1], y, z, sc, py, pz);
+        else
+          hipLaunchKernelGGL((k_sweep<true, false>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
+                             u[(q + 1) & 1], y, z, sc, py, pz);
+      }
+    }
   }
   if (n >= 2) hipLaunchKernelGGL(k_tau_tail, dim3(1), dim3(64), 0, st, tau, n);
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
 
-// workspace of the back-transform: u (n), w (ncols)
+// workspace of the back-transform: w (ncols) and the partial sums
+// (ceil(n / 64) x ncols)
 size_t ormhr_bytes(int n, int ncols) {
-  return align_up(sizeof(double) * (size_t)n) + align_up(sizeof(double) * (size_t)(ncols > 0 ? ncols : 1));
+  const int nc = ncols > 0 ? ncols : 1;
+  return align_up(sizeof(double) * (size_t)nc) + align_up(sizeof(double) * (size_t)nc * cdiv(n, kT));
 }
 
 // Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z)))
 int ormhr(hipStream_t st, int n, const double* A, int lda, const double* tau, int ncols, double* Z, int ldz,
           void* work) {
-  double* u = static_cast<double*>(work);
-  double* w = at<double>(work, align_up(sizeof(double) * (size_t)n));
-  for (int k = n - 3; k >= 0; --k) {
-    const int m = n - k - 1;
-    hipLaunchKernelGGL(k_make_u, dim3((m + 255) / 256), dim3(256), 0, st, A, (long long)lda, n, k, u);
-    hipLaunchKernelGGL(k_dot_cols, dim3((ncols + 3) / 4), dim3(256), 0, st, Z, (long long)ldz, k + 1, m, 0, ncols, u,
-                       w);
-    hipLaunchKernelGGL(k_rank1, tiles(m, ncols), dim3(256), 0, st, Z, (long long)ldz, k + 1, m, 0, ncols, tau, k, u,
-                       w);
+  double* wv = static_cast<double*>(work);
+  double* pw = at<double>(work, align_up(sizeof(double) * (size_t)ncols));
+  const long long la = lda, lz = ldz;
+  const int nct = cdiv(ncols, kT);
+  // partial sums of reflector n-3 (rows n-2 .. n-1)
+  hipLaunchKernelGGL((k_zsweep<false, true>), dim3(cdiv(2, kT), nct), dim3(256), 0, st, A, la, n, n - 2, tau, Z,
+                     lz, ncols, wv, pw);
+  for (int q = n - 3; q >= 0; --q) {
+    const int rows = n - q;  // rows q .. n-1 of this sweep
+    const int nrt_prev = cdiv(n - (q + 1), kT);  // row tiles of the partial sums for reflector q
+    hipLaunchKernelGGL(k_reduce, dim3(cdiv(ncols, kRO)), dim3(256), 0, st, pw, 0, 0, pw, nrt_prev,
+                       (long long)ncols, ncols, wv, wv);
+    const dim3 g(cdiv(rows, kT), nct);
+    if (q >= 1)
+      hipLaunchKernelGGL((k_zsweep<true, true>), g, dim3(256), 0, st, A, la, n, q, tau, Z, lz, ncols, wv, pw);
+    else
+      hipLaunchKernelGGL((k_zsweep<true, false>), g, dim3(256), 0, st, A, la, n, q, tau, Z, lz, ncols, wv, pw);
   }
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
