@@ -85,8 +85,8 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 0 = the tuner's choice for this problem set if it ran,
  *                 else 64.  Critical blocks always take 8 columns.
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
- *                 matrix cores, then an FP64 residual check per shift with a
- *                 fall back to the all-FP64 solve for shifts that fail it.
+ *                 matrix cores, then a residual check per shift with a fall
+ *                 back to the all-FP64 solve for shifts that fail it.
  *   residual      1 = also compute the FP64 normalised residual
  *                 ||H y - lambda y||_2 / (||H||_F ||y||_2) into resid[].
  *   graph         1 = replay the launch sequence as a HIP graph (captured on
@@ -306,9 +306,14 @@ int hsrq_dhsrq3_batched(hsrq_handle_t h, int count, const hsrq_problem_t* proble
  * the handle's stream: (1) the whole solve with the tile-update products in
  * FP32 on the matrix cores (operands scaled by powers of two into FP32 range,
  * FP32 accumulation over a tile; rotations, scale factors, small solves and
- * normalisation stay FP64) and the FP64 normalised residual of every shift;
- * (2) one host synchronisation; a shift passes when it converged and its
- * residual is at most 10 n eps (eps = 2^-52); (3) the shifts that fail are
+ * normalisation stay FP64) and the check value of every shift: the FP64
+ * normalised residual when residuals are requested (resid[] given), else a
+ * sketch of it, ||R^T (H y - lambda y)||_2 / ||H||_F with a fixed n x 8
+ * matrix R of entries +-1/sqrt(8) (an unbiased estimate of the squared
+ * residual, O(8 n) work per shift once R^T H is formed); (2) one host
+ * synchronisation; a shift passes when it converged and its residual is at
+ * most 10 n eps (eps = 2^-52), its sketch at most a quarter of that;
+ * (3) the shifts that fail are
  * solved again from their starting vectors entirely in FP64 and their outputs
  * replace the first pass's.  Shifts flagged singular (2) or with invalid input
  * (3, 4) are final after phase 1.  The call therefore returns only after

@@ -45,6 +45,11 @@ struct ProbDesc {
   // column) RPART[jt * n + row], sums of h^2 per tile pair HFP[i * N + jt],
   // residual sums of squares per (64-row block, column) RNUMP[rb * ld + col]
   double *RPART, *HFP, *RNUMP;
+  // sketched residual (mixed precision's check): probe entries RK[k * n + i],
+  // the sketch of H SK[k * n + j] = sum_i RK[k][i] h(i, j), and per 64-row
+  // block the partial sums SKP[(rb * 16 + q) * ld + col] of RK y (q < 8) and
+  // SK y (q >= 8)
+  double *RK, *SK, *SKP;
   // zero-initialised per call: ||H||_F^2 (written by the reduction), flags,
   // ||H||_inf (a maximum of non-negative doubles, taken on their bit patterns)
   double* HF;

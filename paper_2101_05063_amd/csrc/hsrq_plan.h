@@ -38,6 +38,10 @@ void launch_far(int nb, int prec, int l3rot, int fcb, const ProbDesc* d, const T
 void launch_final(const ProbDesc* d, const int2* cblk, int ncblk, const int4* fblk, int nfblk, hipStream_t st);
 void launch_output(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 void launch_resid(const ProbDesc* d, const int4* blk, int nblk, const int2* cblk, int ncblk, hipStream_t st);
+// the sketched residual: skb lists (problem, 64-column tile of H), blk the
+// (problem, 64-row block, column block) triples, cblk the column blocks
+void launch_sketch(const ProbDesc* d, const int2* skb, int nskb, const int4* blk, int nblk, const int2* cblk,
+                   int ncblk, hipStream_t st);
 void launch_fill(double* p, long long cnt, double v, hipStream_t st);
 void launch_copy(const CopyEnt* ents, int count, hipStream_t st);
 void launch_gate(hipStream_t st);
@@ -59,7 +63,7 @@ struct ProbPlan {
   // byte offsets inside the workspace
   size_t o_meta_d, o_meta_i;              // head: lam_re, lam_im | 4 int arrays
   size_t o_V, o_X, o_Y, o_C, o_S, o_PHI, o_Z[2], o_W[2], o_BMAX, o_VMAX, o_BSSQ, o_BCMX, o_TN, o_FIN, o_AX, o_AMAX;
-  size_t o_zero, o_HF, o_FLAG, o_HN, o_RPART, o_HFP, o_RNUMP;
+  size_t o_zero, o_HF, o_FLAG, o_HN, o_RPART, o_HFP, o_RNUMP, o_RK, o_SK, o_SKP;
 };
 
 struct Plan {
@@ -73,7 +77,8 @@ struct Plan {
   std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges
   std::vector<int2> blk_cols;
   std::vector<int4> blk_prep, blk_init, blk_out, blk_fin;
-  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin;
+  std::vector<int2> blk_skh;  // (problem, 64-column tile of H): the sketch of H
+  size_t o_desc, o_tasks, o_bprep, o_bcols, o_binit, o_bout, o_bfin, o_bskh;
   size_t head_bytes, total_bytes;
   size_t o_zero_all = 0, zero_count = 0;  // doubles
   int nmax = 0;                           // largest order

@@ -136,3 +136,35 @@ def test_mixed_batch_of_passing_and_failing(solver):
             assert np.array_equal(Y1[:, l], Y0[:, l])
         compare(Y1, o1[0].cpu().numpy(), o1[1].cpu().numpy(), o1[2].cpu().numpy(), Yo, Eo, muo, infoo, wi,
                 sel=[0, 1, 2], dir_tol=1e-9, mu_tol=1e-2, straddle_tol=1e-2)
+
+
+def test_sketched_check_c2(solver):
+    """Without residuals requested, the mixed-precision check is the sketch
+    ||R^T (H y - lambda y)|| / ||H||_F (8 fixed +-1/sqrt(8) probes) against a
+    quarter of 10 n eps.  On C2 every returned result must still meet the
+    FP64 residual bar (computed here on the host) and the same bars against
+    the reference as with the full check.  The sketched check is the more
+    conservative one (a shift whose residual lies between about a sixth of
+    the bar and the bar passes the full check and fails the sketched one),
+    so it may send more shifts to the FP64 fallback, but hardly fewer: a
+    sketch that underestimated residuals would let failing shifts through."""
+    c = g.config_c2()
+    H, wr, wi, B = c["H"], c["wr"], c["wi"], c["B"]
+    n = H.shape[0]
+    run(solver, H, wr, wi, B, precision=1)
+    nfb_full = solver.fallback_count()
+    print(f"[gpu] sketched check: n={n} m={len(wr)}", flush=True)
+    Y = dev(B)
+    E, mu, info, _ = solver.dhsrq3(dev(H), wr, wi, Y, precision=1, residual=False)
+    torch.cuda.synchronize()
+    nfb = solver.fallback_count()
+    Yg, Eg, mug, infog = host(Y), E.cpu().numpy(), mu.cpu().numpy(), info.cpu().numpy()
+    print(f"fallbacks: sketched check {nfb}, full check {nfb_full} of {len(wr)}")
+    assert nfb >= nfb_full - 2
+    res = O.residual(H, wr, wi, Yg)
+    conv = infog == 0
+    assert np.all(res[conv] <= 10 * n * EPS), res[conv].max()
+    Yo, Eo, muo, infoo = O.batch(H, wr, wi, B)
+    sep, nh = c["sep"], c["norm2"]
+    good = [l for l in range(len(wr)) if sep[l] >= 1e-3 * nh]
+    compare(Yg, Eg, mug, infog, Yo, Eo, muo, infoo, wi, sel=good, mu_tol=1e-2, straddle_tol=1e-2)
