@@ -586,6 +586,9 @@ def main():
                     help="c3: the headline single-matrix solve; c4: 512 matrices of uneven order in one "
                          "graph launch (batching); c5: the serving loop under Poisson arrivals")
     ap.add_argument("--requests", type=int, default=2000, help="c5: open-loop arrivals")
+    ap.add_argument("--share-min-far", type=int, default=0,
+                    help="c3: far-tile blocks from which a step uses the CU-sharing critical kernel (0 = default)")
+    ap.add_argument("--cols-per-block", type=int, default=0, help="c3: far-block width (0 = default)")
     ap.add_argument("--hess-n", type=int, default=8000, help="hessenberg: matrix order")
     ap.add_argument("--hess-cols", type=int, default=1000, help="hessenberg: vectors back-transformed")
     ap.add_argument("--serving-requests", type=int, default=300,
@@ -725,7 +728,8 @@ def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
             A.copy_(Bd)
         torch.cuda.synchronize()
         for k in range(args.warmup):
-            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph, rotations=rotations)
+            solver.dhsrq3(Hd, wr, wi, Xw[k], nb=nb, precision=args.precision, graph=graph, rotations=rotations,
+                          share_min_far=args.share_min_far, cols_per_block=args.cols_per_block)
         torch.cuda.synchronize()
         if prof:
             solver.profile(True)
@@ -735,7 +739,8 @@ def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
         outs = []
         for k in range(args.steps):
             outs.append(solver.dhsrq3(Hd, wr, wi, Xs[k], nb=nb, precision=args.precision, graph=graph,
-                                      rotations=rotations))
+                                      rotations=rotations, share_min_far=args.share_min_far,
+                                      cols_per_block=args.cols_per_block))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pr = None
@@ -756,8 +761,9 @@ def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
         if kind == "far":
-            # the library's default far-block width (64 columns) at this size
-            name = f"hsrq::k_far3<{nbv}, 64>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
+            # the far-block width: the library's default (64 columns) at this size
+            cbv = args.cols_per_block if args.cols_per_block in (32, 64) else 64
+            name = f"hsrq::k_far3<{nbv}, {cbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
         else:
             # steps with many far-tile blocks use the variant that shares its CU
             tmpl = f"<{nbv}, {f32}, {'true' if l3 else 'false'}>"
