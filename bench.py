@@ -761,8 +761,8 @@ def run_c3_form(solver, Hd, Bd, wr, wi, nb, nbv, rotations, fl, args):
         ms_k, launches = prof[kind]
         per_solve = ms_k / args.steps
         if kind == "far":
-            # the far-block width: the library's default (64 columns) at this size
-            cbv = args.cols_per_block if args.cols_per_block in (32, 64) else 64
+            # the far-block width: the library default (32 columns in the level-3 form, 64 otherwise)
+            cbv = args.cols_per_block if args.cols_per_block in (32, 64) else (32 if l3 else 64)
             name = f"hsrq::k_far3<{nbv}, {cbv}>" if l3 else f"hsrq::k_far<{nbv}, {f32}>"
         else:
             # steps with many far-tile blocks use the variant that shares its CU

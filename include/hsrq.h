@@ -83,7 +83,8 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *   cols_per_block columns (shifts) per far-tile block, the b_c of Sec. 3.2:
  *                 64, or 32 in the level-3 form (rotations 1, precision 0);
  *                 0 = the tuner's choice for this problem set if it ran,
- *                 else 64.  Critical blocks always take 8 columns.
+ *                 else 32 in the level-3 form and 64 otherwise.  Critical
+ *                 blocks always take 8 columns.
  *   precision     0 = all FP64; 1 = tile-update products in FP32 on the
  *                 matrix cores, then a residual check per shift with a fall
  *                 back to the all-FP64 solve for shifts that fail it.
@@ -99,7 +100,8 @@ typedef struct hsrq_handle_s* hsrq_handle_t;
  *                 variants that compute the same bits: one that takes a
  *                 compute unit to itself and one that leaves room on it for
  *                 one far-tile block.  Steps with at least share_min_far
- *                 far-tile blocks use the second.  0 = the library's default
+ *                 far-tile blocks of 64 columns (two blocks of 32 columns
+ *                 count as one) use the second.  0 = the library's default
  *                 (512), -1 = never; any value >= -1 is accepted.
  *   rotations     how the rotations of a tile column reach the cross-over
  *                 columns of the tile rows above its superdiagonal tile

@@ -83,6 +83,7 @@ void xcd_order(Task* t, int n) {
 void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice, int fcb) {
   P.nb = nb_choice;
   P.fcb = fcb;
+  P.alone = count == 1 ? 1 : 0;
   const int nb = P.nb;
   P.pp.resize(count);
   int Tmax = 0;
@@ -394,13 +395,14 @@ bool opts_ok(const hsrq_opts_t* o) {
 }
 
 // tile size and far-block width: explicit options, else the autotuner's
-// choice for this problem set, else a size rule (and 64 columns)
+// choice for this problem set, else a size rule (and 32 columns in the
+// level-3 form: shorter far-tile blocks leave a shorter tail per step)
 struct Tile {
   int nb, fcb;
 };
 bool l3_form(const hsrq_opts_t* o) { return o && o->rotations == 1 && o->precision == 0; }
 Tile choose_tile(hsrq_handle_t h, int count, const hsrq_problem_t* probs, const hsrq_opts_t* o) {
-  Tile t{heuristic_nb(count, probs), 64};
+  Tile t{heuristic_nb(count, probs), 32};
   if (h && !h->tuned.empty()) {
     const uint64_t key = problem_signature(count, probs);
     for (auto& e : h->tuned)
@@ -520,7 +522,8 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
     }
     if (P.ccnt[t] > 0) {
       ProfScope ps(h, HSRQ_K_CRIT, s, true);
-      launch_crit(P.nb, P.prec, P.l3rot, P.fcnt[t] >= P.share, dd, dt + P.coff[t], P.ccnt[t], s, ps.a, ps.b);
+      launch_crit(P.nb, P.prec, P.l3rot, share_step(P.fcnt[t], P.fcb, P.share) ? 1 : P.alone ? 2 : 0, dd, dt + P.coff[t],
+                  P.ccnt[t], s, ps.a, ps.b);
     }
     if (P.fcnt[t] > 0) {
       if (t > 0) launch_gate(a);  // let the critical kernel reach the CUs first
@@ -564,6 +567,7 @@ uint64_t plan_signature(const Plan& P, int count, void* work, bool want_res) {
   g.add((uint64_t)P.nb);
   g.add((uint64_t)(P.prec * 2 + P.l3rot));
   g.add((uint64_t)(uint32_t)P.share);
+  g.add((uint64_t)P.alone);
   g.add((uint64_t)P.fcb);
   g.add((uint64_t)count);
   g.add((uint64_t)reinterpret_cast<uintptr_t>(work));

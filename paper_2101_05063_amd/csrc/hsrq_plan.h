@@ -20,14 +20,21 @@ void launch_init(const ProbDesc* d, const int4* blk, int nblk, hipStream_t st);
 // device (0, or -1 on a HIP error); called once per handle and server
 int crit_smem_init();
 // share: the critical kernel variant that leaves room on its CU for one
-// far-tile block (used for steps with at least share_min far-tile blocks;
-// kShareFar by default, opts.share_min_far otherwise)
+// far-tile block (used for steps with at least share_min far-tile blocks of
+// 64 columns, two blocks of 32 columns counting as one; kShareFar by
+// default, opts.share_min_far otherwise)
 constexpr int kShareFar = 512;
+inline bool share_step(int nfar_blocks, int fcb, int share_min) {
+  return (long long)nfar_blocks * fcb >= (long long)share_min * 64;
+}
 inline int share_min(const hsrq_opts_t* o) {
   if (!o || o->share_min_far == 0) return kShareFar;
   return o->share_min_far < 0 ? 0x7fffffff : o->share_min_far;
 }
-void launch_crit(int nb, int prec, int l3rot, bool share, const ProbDesc* d, const Task* tasks, int ntasks,
+// cu: 1 = the variant that shares its CU with a far-tile block, 2 = the
+// variant that takes the CU to itself (level-3 form at nb = 128: its block
+// also claims the CU's free shared memory), 0 = the plain variant
+void launch_crit(int nb, int prec, int l3rot, int cu, const ProbDesc* d, const Task* tasks, int ntasks,
                  hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // l3rot = 1 (and prec = 0): rotations of the off-diagonal cross-over columns
 // applied as one product with the folded rotations W; else one at a time
@@ -72,6 +79,7 @@ struct Plan {
   int prec = 0;    // 1: FP32 tile-update products
   int l3rot = 0;   // 1: off-diagonal rotations folded and applied on MFMA (opts.rotations)
   int share = kShareFar;  // far-tile blocks from which a step uses the CU-sharing critical kernel
+  int alone = 0;          // 1: the other steps' critical kernel takes its CU to itself (see launch_crit)
   std::vector<ProbPlan> pp;
   std::vector<Task> tasks;
   std::vector<int> coff, ccnt, foff, fcnt;  // per step: critical and far task ranges

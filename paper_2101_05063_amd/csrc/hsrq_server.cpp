@@ -290,7 +290,7 @@ int tick(hsrq_server_s* S) {
   const ProbDesc* dd = reinterpret_cast<const ProbDesc*>(db);
   for (int pr = 0; pr < 2; ++pr) {
     if (!crit[pr].empty())
-      launch_crit(S->nb, pr, S->opts.rotations, (int)far[pr].size() >= share_min(&S->opts), dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
+      launch_crit(S->nb, pr, S->opts.rotations, share_step((int)far[pr].size(), pr == 0 ? S->fcb : 64, share_min(&S->opts)) ? 1 : 0, dd, reinterpret_cast<const Task*>(db + off[pr]), (int)crit[pr].size(), s);
     if (!far[pr].empty())
       launch_far(S->nb, pr, S->opts.rotations, pr == 0 ? S->fcb : 64, dd, reinterpret_cast<const Task*>(db + off[2 + pr]),
                  (int)far[pr].size(), a);
