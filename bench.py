@@ -240,7 +240,7 @@ def cpu_reference_c3(c, seconds, cores):
     dt = time.perf_counter() - t0
     base = dict(value=len(sel) / dt, unit="eigenvectors/s", cores=cores, kind="oracle", cpu_model=cpu_model(),
                 sample=(f"all {m} shifts of the C3 workload (n={H.shape[0]})" if k == 1 else
-                        f"{len(sel)} of the {m} C3 shifts (every {k}th, n={H.shape[0]})") +
+                        f"{len(sel)} of the {m} C3 shifts (one in {k}, n={H.shape[0]})") +
                        f", {dt:.1f} s wall on {cores} threads")
     return base, sel, (Yo, Eo, muo, infoo)
 
