@@ -94,7 +94,9 @@ void build_plan(Plan& P, int count, const hsrq_problem_t* probs, int nb_choice, 
     q.N = (q.n + nb - 1) / nb;
     q.lay = make_layout(probs[p].m, probs[p].wr, probs[p].wi);
     q.ncols = q.lay.ncols;
-    q.ld = std::max(8, (q.ncols + 7) & ~7);
+    // the rows of the row-major workspace arrays (X, V, ...) start on
+    // 128-byte cache lines, so that a block's row segment is whole lines
+    q.ld = std::max(16, (q.ncols + 15) & ~15);
     q.nblk = (q.ncols + kCB - 1) / kCB;
     q.nfblk = (q.ncols + fcb - 1) / fcb;
     if (q.ncols > 0) Tmax = std::max(Tmax, q.N);
