@@ -104,6 +104,40 @@ def test_rotations_bitwise(solver, n, nb, share):
                 assert np.array_equal(V[s0:e0, c + 1], snap[s0:e0].imag), (l, s0, e0)
 
 
+# The chain's short Givens sequence is taken only where every operand pair
+# of the wave is finite, nonzero and within 2^969 of each other; subdiagonal
+# entries of 1e-300 against O(1) working columns send their pivots to the
+# generic sequence, in full row groups and in the partial group at the top
+# of the tile, and the rotations must still be the reference's bit for bit.
+@pytest.mark.parametrize("nb", [64, 128])
+def test_rotations_bitwise_extreme_operands(solver, nb):
+    n = 300
+    rng = np.random.default_rng(4242 + nb)
+    H = g.random_hessenberg(n, rng)
+    for k in (5, 17, 130, 200, 251, 299):
+        H[k, k - 1] = 1e-300 * (1 if k % 2 else -1)
+    wr, wi = random_shifts(rng, H, 4, 2, neg=True)
+    B = rng.standard_normal((n, g.ncols(wi)))
+    run_gpu(solver, H, wr, wi, B, nb=nb, rotations=0)
+    dv = solver.debug_view(n, wi, nb=nb)
+    C, S, PHI = (dv[k].cpu().numpy() for k in ("C", "S", "PHI"))
+    cols, _ = O.columns_of(wi)
+    for l in range(len(wr)):
+        lam = complex(wr[l], wi[l])
+        conj = wi[l] < 0
+        lam_int = np.conj(lam) if conj else lam
+        b = B[:, cols[l]] + (1j * B[:, cols[l] + 1] if wi[l] != 0 else 0)
+        if conj:
+            b = np.conj(b)
+        r = O.solve1(H, lam_int, b, record=True)
+        c = dv["col_of"][l]
+        assert np.array_equal(C[1:, c], r["c"][1:].real), l
+        assert np.array_equal(S[1:, c], r["s"][1:]), l
+        assert np.array_equal(PHI[1:, c], r["phi"][1:]), l
+        if wi[l] != 0:
+            assert np.array_equal(C[1:, c + 1], r["c"][1:].imag), l
+
+
 # ---------------------------------------------------------------------------
 # solutions: random shifts (far from the spectrum or not), several tilings
 # ---------------------------------------------------------------------------
