@@ -511,7 +511,7 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
   // either kind waits for both kinds of step t-1.  (Letting the next
   // critical step start once only the far tile row next to the diagonal is
   // done was measured slower: the rest of the far tiles then hold the compute
-  // units that the critical blocks, with their 96 KB of shared memory, need.)
+  // units that the critical blocks, with their 83 KB of shared memory, need.)
   const int T = (int)P.coff.size();
   hipStream_t a = h->aux;
   hipEvent_t ev_fork = h->sync_ev[0], ev_crit = h->sync_ev[1], ev_far = h->sync_ev[2];
