@@ -393,10 +393,12 @@ def bench_hessenberg(args):
     """The steps around the solve: Householder reduction of a general n x n
     matrix to Hessenberg form (hsrq_gehrd) and the back-transform of ncols
     vectors (hsrq_ormhr), on seeded standard-normal data.  One step = one
-    reduction plus one back-transform.  Both are HBM-bound: the algorithmic
-    bytes are one read and one write of the trailing matrix per reflector
-    (16 n (n - q - 2) for reflector q) and of the trailing rows of Z
-    (16 (n - q - 1) ncols)."""
+    reduction plus one back-transform.  The reduction is HBM-bound: its
+    algorithmic bytes are one read and one write of the trailing matrix per
+    reflector (16 n (n - q - 2) for reflector q).  The back-transform is
+    blocked (compact WY) and runs as matrix products: its algorithmic flops
+    are those of applying each reflector to the columns, 4 (n - q - 1) ncols
+    for reflector q."""
     import numpy as np
     import torch
 
@@ -429,9 +431,9 @@ def bench_hessenberg(args):
         t_bt += e1.elapsed_time(e2)
     ms_red, ms_bt = t_red / K, t_bt / K
     bytes_red = sum(16.0 * n * (n - q - 2) for q in range(n - 2))
-    bytes_bt = sum(16.0 * (n - q - 1) * ncols for q in range(n - 2))
+    flops_bt = sum(4.0 * (n - q - 1) * ncols for q in range(n - 2))
     gbs_red = bytes_red / (ms_red * 1e-3) / 1e9
-    gbs_bt = bytes_bt / (ms_bt * 1e-3) / 1e9
+    tf_bt = flops_bt / (ms_bt * 1e-3) / 1e12
     # spot check of the last reduction: Q0 orthogonal on a few columns (Q0 e_j
     # from the back-transform of unit vectors)
     E = torch.zeros(n, 4, dtype=torch.float64, device=dev)
@@ -449,8 +451,8 @@ def bench_hessenberg(args):
                    "n": n, "ncols": ncols},
         "reduction": {"ms": round(ms_red, 3), "algorithmic_bytes": bytes_red, "achieved_GBps": round(gbs_red, 1),
                       "frac_hbm_peak": round(gbs_red / PEAK_HBM_GBS, 4)},
-        "back_transform": {"ms": round(ms_bt, 3), "algorithmic_bytes": bytes_bt,
-                           "achieved_GBps": round(gbs_bt, 1), "frac_hbm_peak": round(gbs_bt / PEAK_HBM_GBS, 4)},
+        "back_transform": {"ms": round(ms_bt, 3), "algorithmic_flops": flops_bt,
+                           "achieved_TFLOPs": round(tf_bt, 2), "frac_fp64_peak": round(tf_bt / PEAK_FP64_TFLOPS, 4)},
         "roofline": {"kernel": "hsrq::k_sweep (reduction, whole call)", "bound": "hbm",
                      "achieved": round(gbs_red, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs_red / PEAK_HBM_GBS, 4), "traffic": None},

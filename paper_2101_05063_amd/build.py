@@ -39,7 +39,9 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}")
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # rocBLAS: the GEMMs of the blocked back-transform (hsrq_ormhr)
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

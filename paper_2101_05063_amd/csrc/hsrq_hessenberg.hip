@@ -21,10 +21,12 @@
 //   k_colhouse    s; column k+1 updated; the reflector of column k+1
 //   k_sweep       columns k+2..n-1 updated; partial sums for step k+1
 // Every reduction has a fixed order, so the results are the same on every
-// run.  The back-transform applies the reflectors in reverse order to the
-// columns of Z with the same fusion (k_zsweep, k_reduce).
+// run.  The back-transform is blocked (compact WY): panels of 64 reflectors,
+// each three matrix products on rocBLAS; it is compute-bound, not HBM-bound.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <rocblas/rocblas.h>
 
 #include "hsrq.h"
 #include "hsrq_plan.h"
@@ -256,48 +258,69 @@ __global__ void __launch_bounds__(256) k_reduce(const double* py, int nct, int n
   }
 }
 
-// Back-transform sweep of reflector q over rows q..n-1 of Z (n x ncols),
-// 64 x 64 tiles.  UPD: rows q+1..n-1 -= tau[q] u_q(r) w(c).  ACC: partial
-// column sums of u_{q-1}(r) Z(r, c) over the tile's rows (row q included, it
-// is unchanged by step q) for the next reflector.  u_q(q+1) = 1 and
-// u_q(r) = A(r, q) below; q = n-2 with UPD false starts the recurrence.
-template <bool UPD, bool ACC>
-__global__ void __launch_bounds__(256) k_zsweep(const double* __restrict__ A, long long lda, int n, int q,
-                                                const double* __restrict__ tau, double* __restrict__ Z,
-                                                long long ldz, int ncols, const double* __restrict__ wv,
-                                                double* __restrict__ pw) {
-  __shared__ double zt[4][kCW][kT + 1];
-  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r = q + blockIdx.x * kT + l;  // row tiles start at row q
-  const int cb = blockIdx.y * kT + w * kCW;
-  const bool rok = r < n;
-  const int rr = rok ? r : n - 1;
-  double tur = 0.0, un = 0.0;
-  if (UPD && rok && r >= q + 1) tur = tau[q] * (r == q + 1 ? 1.0 : A[rr + (long long)q * lda]);
-  if (ACC && rok) un = r == q ? 1.0 : A[rr + (long long)(q - 1) * lda];
-  double a[kCW], wj[kCW];
-#pragma unroll
-  for (int j = 0; j < kCW; ++j) {
-    const int c = cb + j < ncols ? cb + j : ncols - 1;
-    a[j] = Z[(long long)c * ldz + rr];
-    if (UPD) wj[j] = wv[c];
-  }
-  double zp[kCW];
-#pragma unroll
-  for (int j = 0; j < kCW; ++j) {
-    const int c = cb + j;
-    const bool cok = c < ncols;  // uniform over the wave
-    if (UPD) {
-      a[j] = fma(-tur, wj[j], a[j]);
-      if (rok && cok && r >= q + 1) Z[(long long)c * ldz + r] = a[j];
+// The back-transform in compact WY form: reflectors j0 .. j0+kb-1 applied
+// together are I - V T V^T (V = [u_j0 .. u_j0+kb-1], T upper triangular,
+// LAPACK's DLARFT, forward and columnwise), so that Z <- (I - V T V^T) Z is
+// three matrix products.  V is zero above row j0+1; the panel holds rows
+// j0+1 .. n-1 only.
+constexpr int kWY = 64;  // reflectors per panel
+
+// V (column-major nr x kb, nr = n - j0 - 1): u_k explicit, 0 above its unit
+// entry at row k+1, A(r, k) below it
+__global__ void __launch_bounds__(256) k_vpanel(const double* __restrict__ A, long long lda, int n, int j0, int kb,
+                                                double* __restrict__ V) {
+  const long long nr = n - (j0 + 1);
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nr * kb) return;
+  const int c = (int)(e / nr);
+  const int i = j0 + 1 + (int)(e - (long long)c * nr);  // the row of A
+  const int k = j0 + c;                                  // the reflector
+  V[e] = i == k + 1 ? 1.0 : (i > k + 1 ? A[i + (long long)k * lda] : 0.0);
+}
+
+// T (column-major kb x kb, zero below the diagonal) from G = V^T V and the
+// panel's tau: T(j, j) = tau_j, T(0:j, j) = T(0:j, 0:j) (-tau_j G(0:j, j)),
+// column by column in order (one block; four threads per row share its dot
+// products, combined in a fixed order)
+__global__ void __launch_bounds__(4 * kWY) k_larft(const double* __restrict__ G, const double* __restrict__ tau,
+                                                   int j0, int kb, double* __restrict__ T) {
+  __shared__ double ts[kWY][kWY + 1];  // ts[row][column]
+  __shared__ double t[kWY];
+  const int i = threadIdx.x >> 2, part = threadIdx.x & 3;
+  for (int c = part; c < kWY; c += 4) ts[i][c] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double tj = tau[j0 + j];
+    if (part == 0 && i < j) t[i] = -tj * G[i + j * kb];
+    __syncthreads();
+    double acc = 0.0;
+    if (i < j)
+      for (int k = i + part; k < j; k += 4) acc = fma(ts[i][k], t[k], acc);
+    acc += __shfl_xor(acc, 1, 64);  // the four parts of a row are lanes 4i .. 4i+3
+    acc += __shfl_xor(acc, 2, 64);
+    if (part == 0) {
+      if (i < j)
+        ts[i][j] = acc;
+      else if (i == j)
+        ts[i][j] = tj;
     }
-    if (ACC) zp[j] = (rok && cok) ? un * a[j] : 0.0;
+    __syncthreads();
   }
-  if (ACC) {
-    const double s = tile_colsum(zt[w], zp);
-    const int c = cb + (l >> 2);
-    if ((l & 3) == 0 && c < ncols) pw[(long long)blockIdx.x * ncols + c] = s;
-  }
+  if (i < kb)
+    for (int c = part; c < kb; c += 4) T[i + c * kb] = ts[i][c];
+}
+
+// the products V^T Z and V^T V are short and wide (64 rows of output over up
+// to n rows of V): they run as a batch over row chunks of kSK rows, and the
+// chunks' partial results are summed in a fixed order
+constexpr int kSK = 512;
+__global__ void __launch_bounds__(256) k_sumsplit(const double* __restrict__ parts, int nparts, long long len,
+                                                  double* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  double acc = 0.0;
+  for (int q = 0; q < nparts; ++q) acc += parts[(long long)q * len + e];
+  out[e] = acc;
 }
 
 __global__ void k_tau_tail(double* tau, int n) {
@@ -352,34 +375,78 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
 
-// workspace of the back-transform: w (ncols) and the partial sums
-// (ceil(n / 64) x ncols)
+// workspace of the back-transform: the panel V (n x 64), G and T (64 x 64),
+// V^T Z and T V^T Z (64 x ncols), and the chunk partials of V^T V and V^T Z
 size_t ormhr_bytes(int n, int ncols) {
-  const int nc = ncols > 0 ? ncols : 1;
-  return align_up(sizeof(double) * (size_t)nc) + align_up(sizeof(double) * (size_t)nc * cdiv(n, kT));
+  const size_t nc = ncols > 0 ? ncols : 1;
+  const size_t nsk = cdiv(n, kSK);
+  return align_up(sizeof(double) * (size_t)n * kWY) + 2 * align_up(sizeof(double) * kWY * kWY) +
+         2 * align_up(sizeof(double) * kWY * nc) + align_up(sizeof(double) * nsk * kWY * kWY) +
+         align_up(sizeof(double) * nsk * kWY * nc);
 }
 
-// Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z)))
-int ormhr(hipStream_t st, int n, const double* A, int lda, const double* tau, int ncols, double* Z, int ldz,
-          void* work) {
-  double* wv = static_cast<double*>(work);
-  double* pw = at<double>(work, align_up(sizeof(double) * (size_t)ncols));
-  const long long la = lda, lz = ldz;
-  const int nct = cdiv(ncols, kT);
-  // partial sums of reflector n-3 (rows n-2 .. n-1)
-  hipLaunchKernelGGL((k_zsweep<false, true>), dim3(cdiv(2, kT), nct), dim3(256), 0, st, A, la, n, n - 2, tau, Z,
-                     lz, ncols, wv, pw);
-  for (int q = n - 3; q >= 0; --q) {
-    const int rows = n - q;  // rows q .. n-1 of this sweep
-    const int nrt_prev = cdiv(n - (q + 1), kT);  // row tiles of the partial sums for reflector q
-    hipLaunchKernelGGL(k_reduce, dim3(cdiv(ncols, kRO)), dim3(256), 0, st, pw, 0, 0, pw, nrt_prev,
-                       (long long)ncols, ncols, wv, wv);
-    const dim3 g(cdiv(rows, kT), nct);
-    if (q >= 1)
-      hipLaunchKernelGGL((k_zsweep<true, true>), g, dim3(256), 0, st, A, la, n, q, tau, Z, lz, ncols, wv, pw);
-    else
-      hipLaunchKernelGGL((k_zsweep<true, false>), g, dim3(256), 0, st, A, la, n, q, tau, Z, lz, ncols, wv, pw);
+namespace {
+// C (kb x m) = V^T B over the nr rows of V (column-major, leading dimension
+// nr) and of B (leading dimension ldb), as a batch over row chunks summed in
+// order; P holds the chunk partials
+bool gemm_tn_split(rocblas_handle bh, hipStream_t st, int kb, int m, int nr, const double* V, const double* B,
+                   int ldb, double* P, double* C) {
+  const double one = 1.0, zero = 0.0;
+  const rocblas_operation tr = rocblas_operation_transpose, nt = rocblas_operation_none;
+  const int full = nr / kSK, rem = nr - full * kSK;
+  const long long len = (long long)kb * m;
+  bool ok = true;
+  if (full > 0)
+    ok = rocblas_dgemm_strided_batched(bh, tr, nt, kb, m, kSK, &one, V, nr, kSK, B, ldb, kSK, &zero, P, kb, len,
+                                       full) == rocblas_status_success;
+  if (ok && rem > 0)
+    ok = rocblas_dgemm(bh, tr, nt, kb, m, rem, &one, V + (long long)full * kSK, nr, B + (long long)full * kSK, ldb,
+                       &zero, P + (long long)full * len, kb) == rocblas_status_success;
+  const int nparts = full + (rem > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_sumsplit, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, P, nparts, len, C);
+  return ok;
+}
+}  // namespace
+
+// Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z))): panels of 64 reflectors from the
+// last one down, each applied as Z(j0+1:n, :) -= V (T (V^T Z(j0+1:n, :)))
+// with the products on rocBLAS (DGEMM on the handle's stream)
+int ormhr(hipStream_t st, void* blas, int n, const double* A, int lda, const double* tau, int ncols, double* Z,
+          int ldz, void* work) {
+  if (!blas) return HSRQ_ERR_HIP;
+  rocblas_handle bh = static_cast<rocblas_handle>(blas);
+  const size_t nsk = cdiv(n, kSK);
+  size_t off = 0;
+  double* V = at<double>(work, off);
+  off += align_up(sizeof(double) * (size_t)n * kWY);
+  double* G = at<double>(work, off);
+  off += align_up(sizeof(double) * kWY * kWY);
+  double* T = at<double>(work, off);
+  off += align_up(sizeof(double) * kWY * kWY);
+  double* W = at<double>(work, off);
+  off += align_up(sizeof(double) * kWY * (size_t)ncols);
+  double* W2 = at<double>(work, off);
+  off += align_up(sizeof(double) * kWY * (size_t)ncols);
+  double* PG = at<double>(work, off);
+  off += align_up(sizeof(double) * nsk * kWY * kWY);
+  double* PW = at<double>(work, off);
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  const rocblas_operation nt = rocblas_operation_none;
+  bool ok = true;
+  for (int jhi = n - 3; jhi >= 0 && ok; jhi -= kWY) {
+    const int j0 = jhi - kWY + 1 > 0 ? jhi - kWY + 1 : 0;
+    const int kb = jhi - j0 + 1;
+    const int nr = n - (j0 + 1);
+    double* Zr = Z + (j0 + 1);
+    hipLaunchKernelGGL(k_vpanel, dim3(cdiv(nr * kb, 256)), dim3(256), 0, st, A, (long long)lda, n, j0, kb, V);
+    ok = ok && gemm_tn_split(bh, st, kb, kb, nr, V, V, nr, PG, G);
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(4 * kWY), 0, st, G, tau, j0, kb, T);
+    ok = ok && gemm_tn_split(bh, st, kb, ncols, nr, V, Zr, ldz, PW, W);
+    ok = ok && rocblas_dgemm(bh, nt, nt, kb, ncols, kb, &one, T, kb, W, kb, &zero, W2, kb) == rocblas_status_success;
+    ok = ok &&
+         rocblas_dgemm(bh, nt, nt, nr, ncols, kb, &mone, V, nr, W2, kb, &one, Zr, ldz) == rocblas_status_success;
   }
+  if (!ok) return HSRQ_ERR_HIP;
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
 
@@ -426,7 +493,7 @@ int hsrq_ormhr(hsrq_handle_t h, int n, const double* A, int lda, const double* t
   if (ldz < n) return -8;
   if (!work || (reinterpret_cast<uintptr_t>(work) & 255) || work_bytes < hsrq::ormhr_bytes(n, ncols)) return -9;
   if (ncols == 0 || n < 3) return HSRQ_OK;
-  return hsrq::ormhr(hsrq::handle_stream(h), n, A, lda, tau, ncols, Z, ldz, work);
+  return hsrq::ormhr(hsrq::handle_stream(h), hsrq::handle_blas(h), n, A, lda, tau, ncols, Z, ldz, work);
 }
 
 }  // extern "C"

@@ -6,6 +6,7 @@
 // enqueues the kernels on the handle's stream.  Nothing is allocated on the
 // device inside a solve.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -347,6 +348,8 @@ struct hsrq_handle_s {
   size_t lists_bytes = 0;
   hipEvent_t lists_ev = nullptr;
   bool lists_pending = false;
+  // rocBLAS handle of the blocked back-transform (created on first use)
+  rocblas_handle blas = nullptr;
 };
 
 namespace {
@@ -929,6 +932,14 @@ namespace hsrq {
 
 int handle_device(hsrq_handle_t h) { return h->device; }
 hipStream_t handle_stream(hsrq_handle_t h) { return h->stream; }
+void* handle_blas(hsrq_handle_t h) {
+  if (!h->blas && rocblas_create_handle(&h->blas) != rocblas_status_success) {
+    h->blas = nullptr;
+    return nullptr;
+  }
+  if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success) return nullptr;
+  return h->blas;
+}
 bool opts_valid(const hsrq_opts_t* o) { return opts_ok(o); }
 
 // The single-problem solve (precision 0) in the given workspace with nothing
@@ -1249,6 +1260,7 @@ int hsrq_destroy(hsrq_handle_t h) {
   }
   if (h->staging) hipHostFree(h->staging);
   if (h->staging_ev) hipEventDestroy(h->staging_ev);
+  if (h->blas) rocblas_destroy_handle(h->blas);
   delete h;
   return HSRQ_OK;
 }

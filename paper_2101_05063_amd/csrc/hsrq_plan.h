@@ -114,6 +114,9 @@ bool opts_valid(const hsrq_opts_t* o);
 int scratch_init(int device);
 int handle_device(hsrq_handle_t h);
 hipStream_t handle_stream(hsrq_handle_t h);
+// the handle's rocBLAS handle (a rocblas_handle, created on first use, on
+// the handle's stream); null if rocBLAS could not create it
+void* handle_blas(hsrq_handle_t h);
 int run_noalloc(hsrq_handle_t h, const hsrq_problem_t& p, void* work, size_t work_bytes, const hsrq_opts_t* o);
 
 template <class T>
