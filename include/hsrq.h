@@ -267,9 +267,12 @@ int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
  * eigenvector z = Q0 x of A.  Q0 = H_0 H_1 ... H_{n-3}, H_k = I - tau_k u_k
  * u_k^T, u_k zero above row k+1, u_k(k+1) = 1; the layout is LAPACK's DGEHRD
  * one, with H_k A(k+1:n, k) = beta e_1 and beta = -sign(A(k+1, k)) times the
- * norm of A(k+1:n, k).  Unblocked (one reflector at a time; each step is
- * one read and one write of the trailing matrix, which also forms the
- * products the next reflector needs), asynchronous on the handle's stream,
+ * norm of A(k+1:n, k).  The reduction is unblocked (one reflector at a
+ * time; each step is one read and one write of the trailing matrix, which
+ * also forms the products the next reflector needs); the back-transform is
+ * blocked (panels of 64 reflectors applied as Z -= V T V^T Z, compact WY,
+ * the products on rocBLAS DGEMM on the handle's stream; a rocBLAS handle is
+ * created on the first call).  Both are asynchronous on the handle's stream,
  * workspace from the caller (256-byte aligned).  Run-to-run deterministic.
  *
  * hsrq_gehrd: A (device, n x n, lda >= n) in: general; out: H on and above
@@ -279,7 +282,8 @@ int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
  *   Statuses -1 .. -6 for an invalid h, n, A, lda, tau, work.
  * hsrq_ormhr: Z (device, n x ncols, ldz >= n) <- Q0 Z, with A and tau as
  *   hsrq_gehrd left them.  Statuses -1 .. -9 for an invalid h, n, A, lda,
- *   tau, ncols, Z, ldz, work.
+ *   tau, ncols, Z, ldz, work; HSRQ_ERR_HIP if rocBLAS cannot be set up or a
+ *   product fails.
  */
 int hsrq_gehrd_workspace_size(hsrq_handle_t h, int n, size_t* bytes);
 int hsrq_gehrd(hsrq_handle_t h, int n, double* A, int lda, double* tau, void* work, size_t work_bytes);
