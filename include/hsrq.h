@@ -270,7 +270,7 @@ int hsrq_hsrq3in(hsrq_handle_t h, int n, const double* H, int ldh,
  * norm of A(k+1:n, k).  The reduction is unblocked (one reflector at a
  * time; each step is one read and one write of the trailing matrix, which
  * also forms the products the next reflector needs); the back-transform is
- * blocked (panels of 64 reflectors applied as Z -= V T V^T Z, compact WY,
+ * blocked (panels of 128 reflectors applied as Z -= V T V^T Z, compact WY,
  * the products on rocBLAS DGEMM on the handle's stream; a rocBLAS handle is
  * created on the first call).  Both are asynchronous on the handle's stream,
  * workspace from the caller (256-byte aligned).  Run-to-run deterministic.

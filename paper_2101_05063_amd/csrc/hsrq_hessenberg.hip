@@ -21,8 +21,8 @@
 //   k_colhouse    s; column k+1 updated; the reflector of column k+1
 //   k_sweep       columns k+2..n-1 updated; partial sums for step k+1
 // Every reduction has a fixed order, so the results are the same on every
-// run.  The back-transform is blocked (compact WY): panels of 64 reflectors,
-// each three matrix products on rocBLAS; it is compute-bound, not HBM-bound.
+// run.  The back-transform is blocked (compact WY): panels of 128
+// reflectors, each applied with matrix products on rocBLAS.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(256) k_reduce(const double* py, int nct, int n
 // LAPACK's DLARFT, forward and columnwise), so that Z <- (I - V T V^T) Z is
 // three matrix products.  V is zero above row j0+1; the panel holds rows
 // j0+1 .. n-1 only.
-constexpr int kWY = 64;  // reflectors per panel
+constexpr int kWY = 128;  // reflectors per panel (T's block: 132 KB of shared memory)
 
 // V (column-major nr x kb, nr = n - j0 - 1): u_k explicit, 0 above its unit
 // entry at row k+1, A(r, k) below it
@@ -279,41 +279,44 @@ __global__ void __launch_bounds__(256) k_vpanel(const double* __restrict__ A, lo
 }
 
 // T (column-major kb x kb, zero below the diagonal) from G = V^T V and the
-// panel's tau: T(j, j) = tau_j, T(0:j, j) = T(0:j, 0:j) (-tau_j G(0:j, j)),
-// column by column in order (one block; four threads per row share its dot
-// products, combined in a fixed order)
+// panel's tau: T(i, i) = tau_i and, for i < j, T(i, j) = -tau_j times the
+// sum over i <= k < j of T(i, k) G(k, j).  Row i of T needs only its own
+// earlier entries, so the rows run side by side in one block, four threads
+// per row; a thread only reads the entries of its row that it wrote itself
+// (k = i + part mod 4), and the four partial sums are combined in a fixed
+// order.
 __global__ void __launch_bounds__(4 * kWY) k_larft(const double* __restrict__ G, const double* __restrict__ tau,
                                                    int j0, int kb, double* __restrict__ T) {
-  __shared__ double ts[kWY][kWY + 1];  // ts[row][column]
-  __shared__ double t[kWY];
+  // s[r][c]: T(r, c) on and above the diagonal, G(r, c) below it (G is symmetric)
+  __shared__ double s[kWY][kWY + 1];
+  __shared__ double tv[kWY];
   const int i = threadIdx.x >> 2, part = threadIdx.x & 3;
-  for (int c = part; c < kWY; c += 4) ts[i][c] = 0.0;
+  for (int e = threadIdx.x; e < kb * kb; e += 4 * kWY) {
+    const int r = e % kb, c = e / kb;
+    if (r > c) s[r][c] = G[e];
+  }
+  if (threadIdx.x < kb) tv[threadIdx.x] = tau[j0 + threadIdx.x];
+  if (part == 0 && i < kb) s[i][i] = tau[j0 + i];
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const double tj = tau[j0 + j];
-    if (part == 0 && i < j) t[i] = -tj * G[i + j * kb];
-    __syncthreads();
+  for (int j = 1; j < kb; ++j) {
     double acc = 0.0;
     if (i < j)
-      for (int k = i + part; k < j; k += 4) acc = fma(ts[i][k], t[k], acc);
+      for (int k = i + part; k < j; k += 4) acc = fma(s[i][k], s[j][k], acc);
     acc += __shfl_xor(acc, 1, 64);  // the four parts of a row are lanes 4i .. 4i+3
     acc += __shfl_xor(acc, 2, 64);
-    if (part == 0) {
-      if (i < j)
-        ts[i][j] = acc;
-      else if (i == j)
-        ts[i][j] = tj;
-    }
-    __syncthreads();
+    if (i < j && ((j - i) & 3) == part) s[i][j] = -tv[j] * acc;
   }
-  if (i < kb)
-    for (int c = part; c < kb; c += 4) T[i + c * kb] = ts[i][c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kb * kb; e += 4 * kWY) {
+    const int r = e % kb, c = e / kb;
+    T[e] = r <= c ? s[r][c] : 0.0;
+  }
 }
 
-// the products V^T Z and V^T V are short and wide (64 rows of output over up
-// to n rows of V): they run as a batch over row chunks of kSK rows, and the
+// the products V^T Z and V^T V are short and wide (kWY rows of output over
+// up to n rows of V): they run as a batch over row chunks of kSK rows, and the
 // chunks' partial results are summed in a fixed order
-constexpr int kSK = 512;
+constexpr int kSK = 256;
 __global__ void __launch_bounds__(256) k_sumsplit(const double* __restrict__ parts, int nparts, long long len,
                                                   double* __restrict__ out) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -375,8 +378,9 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
 
-// workspace of the back-transform: the panel V (n x 64), G and T (64 x 64),
-// V^T Z and T V^T Z (64 x ncols), and the chunk partials of V^T V and V^T Z
+// workspace of the back-transform: the panel V (n x kWY), G and T (kWY x
+// kWY), V^T Z and T V^T Z (kWY x ncols), and the chunk partials of V^T V and
+// V^T Z
 size_t ormhr_bytes(int n, int ncols) {
   const size_t nc = ncols > 0 ? ncols : 1;
   const size_t nsk = cdiv(n, kSK);
@@ -408,8 +412,8 @@ bool gemm_tn_split(rocblas_handle bh, hipStream_t st, int kb, int m, int nr, con
 }
 }  // namespace
 
-// Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z))): panels of 64 reflectors from the
-// last one down, each applied as Z(j0+1:n, :) -= V (T (V^T Z(j0+1:n, :)))
+// Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z))): panels of kWY reflectors from
+// the last one down, each applied as Z(j0+1:n, :) -= V (T (V^T Z(j0+1:n, :)))
 // with the products on rocBLAS (DGEMM on the handle's stream)
 int ormhr(hipStream_t st, void* blas, int n, const double* A, int lda, const double* tau, int ncols, double* Z,
           int ldz, void* work) {
