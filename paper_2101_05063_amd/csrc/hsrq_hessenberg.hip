@@ -163,6 +163,133 @@ __device__ __forceinline__ double tile_colsum(double (*zt)[kT + 1], const double
   return s;
 }
 
+// k_colhouse for n <= R kCH: the column lives in registers (thread t owns
+// rows t + j kCH, j < R), so it is read once and written once.  The same
+// steps as k_colhouse, with the norm of x taken in one pass (sum of squares
+// and largest magnitude reduced together) and redone with a power-of-two
+// scale only when the largest magnitude lies outside [2^-480, 2^480], where
+// a square could overflow or lose to underflow; row c+1 (alpha, then beta)
+// is written by the thread that owns it.
+template <int R>
+__global__ void __launch_bounds__(kCH) k_colhouse_r(double* A, long long lda, int n, int q, double* tau,
+                                                    const double* uq, double* un, const double* y,
+                                                    const double* z, double* sc) {
+  __shared__ double red0[kCH / 64], red1[kCH / 64], red2[kCH / 64], red3[kCH / 64];
+  __shared__ double alpha_s;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = q + 1;  // the column updated here and reduced next
+  const bool refl = c <= n - 3;
+  double* col = A + (long long)c * lda;
+  double a[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int r = tid + j * kCH;
+    a[j] = r < n ? col[r] : 0.0;
+  }
+  if (q >= 0) {
+    // y and u of the thread's rows stay in registers beside the column (84
+    // registers per lane at R = 8, of the 128 a 1024-thread block allows)
+    double yv[R], uv[R], sp = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int r = tid + j * kCH;
+      const double yr = r < n ? y[r] : 0.0;
+      const double ur = (r < n && r >= q + 1) ? uq[r - (q + 1)] : 0.0;
+      yv[j] = yr;
+      uv[j] = ur;
+      sp = fma(ur, yr, sp);
+    }
+    sp = wsum(sp);
+    if (lane == 0) red0[w] = sp;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < kCH / 64; ++j) s += red0[j];
+    const double t = tau[q];
+    if (tid == 0) sc[0] = s;
+    const double u0 = uq[0];
+    const double w0 = fma(-(t * s), u0, z[0]);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int r = tid + j * kCH;
+      a[j] = rank2(a[j], t * yv[j], u0, t * uv[j], w0);
+      if (r < n && (!refl || r <= c)) col[r] = a[j];
+    }
+  }
+  if (!refl) return;  // no reflector for this column
+  double ss = 0.0, mx = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int r = tid + j * kCH;
+    if (r == c + 1) alpha_s = a[j];
+    if (r >= c + 2 && r < n) {
+      ss = fma(a[j], a[j], ss);
+      mx = fmax(mx, fabs(a[j]));
+    }
+  }
+  ss = wsum(ss);
+  mx = wmax(mx);
+  if (lane == 0) {
+    red1[w] = ss;
+    red2[w] = mx;
+  }
+  __syncthreads();  // also publishes alpha_s
+  ss = 0.0;
+  mx = 0.0;
+  for (int j = 0; j < kCH / 64; ++j) {
+    ss += red1[j];
+    mx = fmax(mx, red2[j]);
+  }
+  double xnorm = 0.0;
+  if (mx > 0.0) {
+    if (mx >= 0x1p-480 && mx <= 0x1p480) {
+      xnorm = sqrt(ss);
+    } else {  // scaled by 2^-e, exact
+      const int e = ilogb(mx);
+      double s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int r = tid + j * kCH;
+        if (r >= c + 2 && r < n) {
+          const double v = ldexp(a[j], -e);
+          s2 = fma(v, v, s2);
+        }
+      }
+      s2 = wsum(s2);
+      if (lane == 0) red3[w] = s2;
+      __syncthreads();
+      s2 = 0.0;
+      for (int j = 0; j < kCH / 64; ++j) s2 += red3[j];
+      xnorm = ldexp(sqrt(s2), e);
+    }
+  }
+  const double alpha = alpha_s;
+  double t = 0.0, beta = alpha, scal = 0.0;
+  if (xnorm != 0.0) {
+    // |beta| = hypot(alpha, xnorm), written out with a power-of-two scale
+    const double big = fmax(fabs(alpha), xnorm);
+    const int e = ilogb(big);
+    const double as = ldexp(alpha, -e), xs = ldexp(xnorm, -e);
+    const double rr = ldexp(sqrt(fma(as, as, xs * xs)), e);
+    beta = alpha >= 0.0 ? -rr : rr;
+    t = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int r = tid + j * kCH;
+    if (r == c + 1) col[r] = beta;
+    if (r >= c + 2 && r < n) {
+      const double v = a[j] * scal;
+      col[r] = v;
+      un[r - (c + 1)] = v;
+    }
+  }
+  if (tid == 0) {
+    tau[c] = t;
+    un[0] = 1.0;
+  }
+}
+
 // The sweep of step k over columns k+2..n-1 (all rows), 64 x 64 tiles: lane
 // = row, wave w = 16 columns.  UPD: apply step k (tau[k], u0 = u_k, y, z, s).
 // ACC: partial sums for step k+1 (u1 = u_{k+1}): py[ct][r] = sum over the
@@ -229,28 +356,31 @@ __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long
 }
 
 // y(i) = sum_ct py[ct][i] (i < ny; rows of py ny apart), z(c) = sum_rt
-// pz[rt][c] (c < m; rows of pz lz apart).  A block sums 64 outputs; its 4
-// waves each sum every 4th partial (in order) and the 4 sums are added in
-// a fixed order, so the result does not depend on the schedule.
-constexpr int kRO = 64;  // outputs per reduction block
-__global__ void __launch_bounds__(256) k_reduce(const double* py, int nct, int ny, const double* pz, int nrt,
-                                                long long lz, int m, double* y, double* z) {
-  __shared__ double part[4][kRO];
-  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+// pz[rt][c] (c < m; rows of pz lz apart).  A block sums 32 outputs; its 8
+// groups of 32 threads each sum every 8th partial (in order) and the 8 sums
+// are added in a fixed order, so the result does not depend on the
+// schedule.
+constexpr int kRO = 32;  // outputs per reduction block
+constexpr int kRG = 8;   // partial groups per output
+__global__ void __launch_bounds__(kRO * kRG) k_reduce(const double* py, int nct, int ny, const double* pz, int nrt,
+                                                      long long lz, int m, double* y, double* z) {
+  __shared__ double part[kRG][kRO];
+  const int o = threadIdx.x % kRO, g = threadIdx.x / kRO;
   const int i = blockIdx.x * kRO + o;
   double s = 0.0;
   if (i < ny) {
-#pragma unroll 8
-    for (int ct = g; ct < nct; ct += 4) s += py[(long long)ct * ny + i];
+#pragma unroll 4
+    for (int ct = g; ct < nct; ct += kRG) s += py[(long long)ct * ny + i];
   } else if (i < ny + m) {
     const int c = i - ny;
-#pragma unroll 8
-    for (int rt = g; rt < nrt; rt += 4) s += pz[rt * lz + c];
+#pragma unroll 4
+    for (int rt = g; rt < nrt; rt += kRG) s += pz[rt * lz + c];
   }
   part[g][o] = s;
   __syncthreads();
   if (g == 0 && i < ny + m) {
-    const double t = (part[0][o] + part[1][o]) + (part[2][o] + part[3][o]);
+    const double t = ((part[0][o] + part[1][o]) + (part[2][o] + part[3][o])) +
+                     ((part[4][o] + part[5][o]) + (part[6][o] + part[7][o]));
     if (i < ny)
       y[i] = t;
     else
@@ -341,6 +471,24 @@ size_t gehrd_bytes(int n) {
   return 4 * v + align_up(sizeof(double) * 8) + 2 * align_up(sizeof(double) * (size_t)n * cdiv(n, kT));
 }
 
+namespace {
+// k_colhouse with the column in registers where it fits (n <= 8 kCH)
+void colhouse(hipStream_t st, double* A, long long ld, int n, int q, double* tau, const double* uq, double* un,
+              const double* y, const double* z, double* sc) {
+  const int rows = cdiv(n, kCH);
+  if (rows <= 1)
+    hipLaunchKernelGGL(k_colhouse_r<1>, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, uq, un, y, z, sc);
+  else if (rows <= 2)
+    hipLaunchKernelGGL(k_colhouse_r<2>, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, uq, un, y, z, sc);
+  else if (rows <= 4)
+    hipLaunchKernelGGL(k_colhouse_r<4>, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, uq, un, y, z, sc);
+  else if (rows <= 8)
+    hipLaunchKernelGGL(k_colhouse_r<8>, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, uq, un, y, z, sc);
+  else  // 16 rows per thread would spill at 128 registers per lane
+    hipLaunchKernelGGL(k_colhouse, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, uq, un, y, z, sc);
+}
+}  // namespace
+
 int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   const size_t v = align_up(sizeof(double) * (size_t)n);
   double* u[2] = {static_cast<double*>(work), at<double>(work, v)};
@@ -353,15 +501,14 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   const int nrt = cdiv(n, kT);
   if (n >= 3) {
     // the reflector of column 0 and the partial sums of step 0
-    hipLaunchKernelGGL(k_colhouse, dim3(1), dim3(kCH), 0, st, A, ld, n, -1, tau, u[1], u[0], y, z, sc);
+    colhouse(st, A, ld, n, -1, tau, u[1], u[0], y, z, sc);
     hipLaunchKernelGGL((k_sweep<false, true>), dim3(nrt, cdiv(n - 1, kT)), dim3(256), 0, st, A, ld, n, -1, tau,
                        u[1], u[0], y, z, sc, py, pz);
     for (int q = 0; q <= n - 3; ++q) {
       const int m = n - q - 1;  // rows and columns q+1 .. n-1
-      hipLaunchKernelGGL(k_reduce, dim3(cdiv(n + m, kRO)), dim3(256), 0, st, py, cdiv(m, kT), n, pz, nrt,
+      hipLaunchKernelGGL(k_reduce, dim3(cdiv(n + m, kRO)), dim3(kRO * kRG), 0, st, py, cdiv(m, kT), n, pz, nrt,
                          (long long)n, m, y, z);
-      hipLaunchKernelGGL(k_colhouse, dim3(1), dim3(kCH), 0, st, A, ld, n, q, tau, u[q & 1], u[(q + 1) & 1], y, z,
-                         sc);
+      colhouse(st, A, ld, n, q, tau, u[q & 1], u[(q + 1) & 1], y, z, sc);
       const int nc = n - q - 2;  // columns q+2 .. n-1
       if (nc > 0) {
         const dim3 g(nrt, cdiv(nc, kT));

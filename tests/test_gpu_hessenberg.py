@@ -101,3 +101,39 @@ def test_eigenvectors_of_a_general_matrix(solver):
             assert direction(z, V[:, k]) >= 1.0 - 1e-10, (l, 1.0 - direction(z, V[:, k]))
             checked += 1
     assert checked >= 4
+
+
+@pytest.mark.parametrize("n", [2100, 4500, 8200])
+def test_gehrd_large_properties(solver, n):
+    """The sizes whose column kernel differs from the small cases' (4 and 8
+    rows per thread in registers, and the general kernel past 8192 rows),
+    checked by properties that hold at any size, on the GPU in FP64:
+    Q0 orthogonal, Q0^T A Q0 = H, and the first reflector equal to the one
+    Householder's construction gives for column 0 of A (it depends on that
+    column alone: beta = -sign(a) ||x||, tau = (beta - a) / beta, v = x(2:)
+    / (a - beta), x = A(1:n, 0), a = x(1))."""
+    rng = np.random.default_rng(9000 + n)
+    A = rng.standard_normal((n, n))
+    print(f"[gpu] gehrd properties n={n}", flush=True)
+    Ad = dev(A)
+    A_gpu = Ad.clone()
+    tau = solver.gehrd(Ad)
+    Q = solver.ormhr(Ad, tau, torch.eye(n, dtype=torch.float64, device=Ad.device).t())  # column-major
+    torch.cuda.synchronize()
+    H = torch.triu(Ad, -1)
+    eye = torch.eye(n, dtype=torch.float64, device=Ad.device)
+    orth = float((Q.t().contiguous() @ Q - eye).abs().max())
+    assert orth <= 20 * n * EPS, orth
+    nA = float(torch.linalg.norm(A_gpu))
+    sim = float((Q.t().contiguous() @ (A_gpu @ Q) - H).abs().max())
+    assert sim <= 100 * n * EPS * nA, (sim, nA)
+    x = A[1:, 0]
+    a = x[0]
+    beta = -np.copysign(np.linalg.norm(x), a)
+    R0 = host(Ad[:, :1])[:, 0]
+    t0 = float(tau[0])
+    assert abs(R0[0] - A[0, 0]) == 0.0
+    assert abs(R0[1] - beta) <= 10 * n * EPS * abs(beta)
+    assert abs(t0 - (beta - a) / beta) <= 10 * n * EPS
+    v = x[1:] / (a - beta)
+    assert np.max(np.abs(R0[2:] - v)) <= 10 * n * EPS * max(1.0, np.abs(v).max())
