@@ -143,23 +143,28 @@ __global__ void __launch_bounds__(kCH) k_colhouse(double* A, long long lda, int 
   (void)m;
 }
 
-// Column sums over the 64 rows of a tile for the CW = 16 columns of a wave:
-// each lane stores its row's products, then 4 lanes per column add 16 rows
-// each and combine the 4 sums, in a fixed order.  Returns the sum of column
-// (lane >> 2) in the lanes with (lane & 3) == 0.
+// Column sums over the 64 rows of a tile for the CW = 16 columns of a wave,
+// through lane exchanges alone (no shared memory): four halving steps over
+// lane bits 5, 4, 3, 2 leave lane l with the sum of column l >> 2 over the
+// 16 lanes that agree with it in those bits... (each step keeps the half of
+// the columns its bit selects and adds the partner's copy of that half),
+// then the 4 lanes of a column are added.  A fixed order, so the result
+// does not depend on the schedule.  Returns the sum of column (lane >> 2)
+// in every lane (the caller stores it from the lanes with (lane & 3) == 0).
 constexpr int kCW = 16;  // columns per wave in the sweeps
-__device__ __forceinline__ double tile_colsum(double (*zt)[kT + 1], const double* v) {
+__device__ __forceinline__ double tile_colsum(const double* v) {
   const int l = threadIdx.x & 63;
+  double w8[8], w4[4], w2[2];
+  const bool b5 = (l & 32) != 0, b4 = (l & 16) != 0, b3 = (l & 8) != 0, b2 = (l & 4) != 0;
 #pragma unroll
-  for (int j = 0; j < kCW; ++j) zt[j][l] = v[j];
-  __builtin_amdgcn_wave_barrier();
-  const int jj = l >> 2, pp = l & 3;
-  double s = 0.0;
+  for (int j = 0; j < 8; ++j) w8[j] = (b5 ? v[j + 8] : v[j]) + __shfl_xor(b5 ? v[j] : v[j + 8], 32, 64);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) s += zt[jj][pp * 16 + i];
+  for (int j = 0; j < 4; ++j) w4[j] = (b4 ? w8[j + 4] : w8[j]) + __shfl_xor(b4 ? w8[j] : w8[j + 4], 16, 64);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) w2[j] = (b3 ? w4[j + 2] : w4[j]) + __shfl_xor(b3 ? w4[j] : w4[j + 2], 8, 64);
+  double s = (b2 ? w2[1] : w2[0]) + __shfl_xor(b2 ? w2[0] : w2[1], 4, 64);
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
-  __builtin_amdgcn_wave_barrier();  // zt is reused by the next call
   return s;
 }
 
@@ -304,7 +309,6 @@ __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long
                                                const double* __restrict__ z, const double* __restrict__ sc,
                                                double* __restrict__ py, double* __restrict__ pz) {
   __shared__ double red[4][kT];
-  __shared__ double zt[4][kCW][kT + 1];
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = blockIdx.x * kT + l;
   const int c0 = k + 2;
@@ -346,7 +350,7 @@ __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long
     }
   }
   if (ACC) {
-    const double zs = tile_colsum(zt[w], zp);
+    const double zs = tile_colsum(zp);
     const int c = cb + (l >> 2);
     if ((l & 3) == 0 && c < n) pz[(long long)blockIdx.x * n + (c - (k + 2))] = zs;
     red[w][l] = ys;
