@@ -415,33 +415,52 @@ __global__ void __launch_bounds__(256) k_vpanel(const double* __restrict__ A, lo
 // T (column-major kb x kb, zero below the diagonal) from G = V^T V and the
 // panel's tau: T(i, i) = tau_i and, for i < j, T(i, j) = -tau_j times the
 // sum over i <= k < j of T(i, k) G(k, j).  Row i of T needs only its own
-// earlier entries, so the rows run side by side in one block, four threads
-// per row; a thread only reads the entries of its row that it wrote itself
-// (k = i + part mod 4), and the four partial sums are combined in a fixed
-// order.
-__global__ void __launch_bounds__(4 * kWY) k_larft(const double* __restrict__ G, const double* __restrict__ tau,
-                                                   int j0, int kb, double* __restrict__ T) {
+// earlier entries, so the rows run side by side in one block, kLP threads
+// per row; thread part p handles the columns k = p mod kLP, reads only the
+// entries of its row that it wrote itself, and takes its columns four at
+// a time (terms outside i <= k < j are zero), so that a step's
+// shared-memory loads are in flight together.  The partial sums are
+// combined in a fixed order.
+constexpr int kLP = 4;          // threads per row of T
+constexpr int kLM = kWY / kLP;  // columns per thread
+__global__ void __launch_bounds__(kLP * kWY) k_larft(const double* __restrict__ G, const double* __restrict__ tau,
+                                                     int j0, int kb, double* __restrict__ T) {
   // s[r][c]: T(r, c) on and above the diagonal, G(r, c) below it (G is symmetric)
   __shared__ double s[kWY][kWY + 1];
   __shared__ double tv[kWY];
-  const int i = threadIdx.x >> 2, part = threadIdx.x & 3;
-  for (int e = threadIdx.x; e < kb * kb; e += 4 * kWY) {
+  const int tid = threadIdx.x, i = tid / kLP, p = tid % kLP;
+  for (int e = tid; e < kb * kb; e += kLP * kWY) {
     const int r = e % kb, c = e / kb;
     if (r > c) s[r][c] = G[e];
   }
-  if (threadIdx.x < kb) tv[threadIdx.x] = tau[j0 + threadIdx.x];
-  if (part == 0 && i < kb) s[i][i] = tau[j0 + i];
+  if (tid < kb) tv[tid] = tau[j0 + tid];
+  if (p == i % kLP && i < kb) s[i][i] = tau[j0 + i];
   __syncthreads();
+  // the wave's rows are i0 .. i0+15: its loop runs over the columns
+  // k = p + kLP t with t from i0 / kLP (a multiple of 4) to the last one
+  // below j, four at a time; partial sum q takes the columns with t = q
+  // mod 4, in increasing t, so the sums do not depend on the wave
+  const int i0 = __builtin_amdgcn_readfirstlane((tid >> 6) * (64 / kLP));
   for (int j = 1; j < kb; ++j) {
-    double acc = 0.0;
-    if (i < j)
-      for (int k = i + part; k < j; k += 4) acc = fma(s[i][k], s[j][k], acc);
-    acc += __shfl_xor(acc, 1, 64);  // the four parts of a row are lanes 4i .. 4i+3
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int thi = (j + kLP - 1) / kLP;
+    for (int t = i0 / kLP; t < thi; t += 4) {
+      const int k0 = p + kLP * t, k1 = k0 + kLP, k2 = k1 + kLP, k3 = k2 + kLP;
+      const bool u0 = k0 >= i && k0 < j, u1 = k1 >= i && k1 < j, u2 = k2 >= i && k2 < j, u3 = k3 >= i && k3 < j;
+      const double r0 = s[i][u0 ? k0 : 0], r1 = s[i][u1 ? k1 : 0], r2 = s[i][u2 ? k2 : 0], r3 = s[i][u3 ? k3 : 0];
+      const double g0 = s[j][u0 ? k0 : 0], g1 = s[j][u1 ? k1 : 0], g2 = s[j][u2 ? k2 : 0], g3 = s[j][u3 ? k3 : 0];
+      a0 = fma(u0 ? r0 : 0.0, g0, a0);
+      a1 = fma(u1 ? r1 : 0.0, g1, a1);
+      a2 = fma(u2 ? r2 : 0.0, g2, a2);
+      a3 = fma(u3 ? r3 : 0.0, g3, a3);
+    }
+    double acc = (a0 + a1) + (a2 + a3);
+    acc += __shfl_xor(acc, 1, 64);  // the kLP = 4 parts of a row are adjacent lanes
     acc += __shfl_xor(acc, 2, 64);
-    if (i < j && ((j - i) & 3) == part) s[i][j] = -tv[j] * acc;
+    if (i < j && p == j % kLP) s[i][j] = -tv[j] * acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kb * kb; e += 4 * kWY) {
+  for (int e = tid; e < kb * kb; e += kLP * kWY) {
     const int r = e % kb, c = e / kb;
     T[e] = r <= c ? s[r][c] : 0.0;
   }
@@ -595,7 +614,7 @@ int ormhr(hipStream_t st, void* blas, int n, const double* A, int lda, const dou
     double* Zr = Z + (j0 + 1);
     hipLaunchKernelGGL(k_vpanel, dim3(cdiv(nr * kb, 256)), dim3(256), 0, st, A, (long long)lda, n, j0, kb, V);
     ok = ok && gemm_tn_split(bh, st, kb, kb, nr, V, V, nr, PG, G);
-    hipLaunchKernelGGL(k_larft, dim3(1), dim3(4 * kWY), 0, st, G, tau, j0, kb, T);
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(kLP * kWY), 0, st, G, tau, j0, kb, T);
     ok = ok && gemm_tn_split(bh, st, kb, ncols, nr, V, Zr, ldz, PW, W);
     ok = ok && rocblas_dgemm(bh, nt, nt, kb, ncols, kb, &one, T, kb, W, kb, &zero, W2, kb) == rocblas_status_success;
     ok = ok &&
