@@ -423,8 +423,22 @@ __global__ void __launch_bounds__(256) k_vpanel(const double* __restrict__ A, lo
 // combined in a fixed order.
 constexpr int kLP = 4;          // threads per row of T
 constexpr int kLM = kWY / kLP;  // columns per thread
-__global__ void __launch_bounds__(kLP * kWY) k_larft(const double* __restrict__ G, const double* __restrict__ tau,
-                                                     int j0, int kb, double* __restrict__ T) {
+// the panels: panel p holds reflectors j0 .. jhi, jhi = n - 3 - p kWY, j0 =
+// max(0, jhi - kWY + 1); npanels(n) of them
+__host__ __device__ inline int npanels(int n) { return n >= 3 ? (n - 2 + kWY - 1) / kWY : 0; }
+__host__ __device__ inline void panel(int n, int p, int& j0, int& kb) {
+  const int jhi = n - 3 - p * kWY;
+  j0 = jhi - kWY + 1 > 0 ? jhi - kWY + 1 : 0;
+  kb = jhi - j0 + 1;
+}
+// one block per panel: G and T of panel p at Gs + p kWY^2 and Ts + p kWY^2,
+// column-major with leading dimension kb
+__global__ void __launch_bounds__(kLP * kWY) k_larft(const double* __restrict__ Gs, const double* __restrict__ tau,
+                                                     int n, double* __restrict__ Ts) {
+  int j0, kb;
+  panel(n, blockIdx.x, j0, kb);
+  const double* G = Gs + (long long)blockIdx.x * kWY * kWY;
+  double* T = Ts + (long long)blockIdx.x * kWY * kWY;
   // s[r][c]: T(r, c) on and above the diagonal, G(r, c) below it (G is symmetric)
   __shared__ double s[kWY][kWY + 1];
   __shared__ double tv[kWY];
@@ -548,13 +562,14 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   return hipGetLastError() == hipSuccess ? HSRQ_OK : HSRQ_ERR_HIP;
 }
 
-// workspace of the back-transform: the panel V (n x kWY), G and T (kWY x
-// kWY), V^T Z and T V^T Z (kWY x ncols), and the chunk partials of V^T V and
-// V^T Z
+// workspace of the back-transform: the panel V (n x kWY), G and T of every
+// panel (kWY x kWY each), V^T Z and T V^T Z (kWY x ncols), and the chunk
+// partials of V^T V and V^T Z
 size_t ormhr_bytes(int n, int ncols) {
   const size_t nc = ncols > 0 ? ncols : 1;
   const size_t nsk = cdiv(n, kSK);
-  return align_up(sizeof(double) * (size_t)n * kWY) + 2 * align_up(sizeof(double) * kWY * kWY) +
+  const size_t np = npanels(n) > 0 ? npanels(n) : 1;
+  return align_up(sizeof(double) * (size_t)n * kWY) + 2 * align_up(sizeof(double) * np * kWY * kWY) +
          2 * align_up(sizeof(double) * kWY * nc) + align_up(sizeof(double) * nsk * kWY * kWY) +
          align_up(sizeof(double) * nsk * kWY * nc);
 }
@@ -584,19 +599,24 @@ bool gemm_tn_split(rocblas_handle bh, hipStream_t st, int kb, int m, int nr, con
 
 // Z <- Q0 Z = H_0 (H_1 ( ... (H_{n-3} Z))): panels of kWY reflectors from
 // the last one down, each applied as Z(j0+1:n, :) -= V (T (V^T Z(j0+1:n, :)))
-// with the products on rocBLAS (DGEMM on the handle's stream)
+// with the products on rocBLAS (DGEMM on the handle's stream).  T depends on
+// the reflectors alone, so a first pass forms G = V^T V of every panel and
+// one launch builds every panel's T, one block per panel; the second pass
+// applies the panels to Z.
 int ormhr(hipStream_t st, void* blas, int n, const double* A, int lda, const double* tau, int ncols, double* Z,
           int ldz, void* work) {
   if (!blas) return HSRQ_ERR_HIP;
   rocblas_handle bh = static_cast<rocblas_handle>(blas);
   const size_t nsk = cdiv(n, kSK);
+  const int np = npanels(n);
+  const size_t npa = np > 0 ? np : 1;
   size_t off = 0;
   double* V = at<double>(work, off);
   off += align_up(sizeof(double) * (size_t)n * kWY);
-  double* G = at<double>(work, off);
-  off += align_up(sizeof(double) * kWY * kWY);
-  double* T = at<double>(work, off);
-  off += align_up(sizeof(double) * kWY * kWY);
+  double* Gs = at<double>(work, off);
+  off += align_up(sizeof(double) * npa * kWY * kWY);
+  double* Ts = at<double>(work, off);
+  off += align_up(sizeof(double) * npa * kWY * kWY);
   double* W = at<double>(work, off);
   off += align_up(sizeof(double) * kWY * (size_t)ncols);
   double* W2 = at<double>(work, off);
@@ -607,14 +627,21 @@ int ormhr(hipStream_t st, void* blas, int n, const double* A, int lda, const dou
   const double one = 1.0, zero = 0.0, mone = -1.0;
   const rocblas_operation nt = rocblas_operation_none;
   bool ok = true;
-  for (int jhi = n - 3; jhi >= 0 && ok; jhi -= kWY) {
-    const int j0 = jhi - kWY + 1 > 0 ? jhi - kWY + 1 : 0;
-    const int kb = jhi - j0 + 1;
+  for (int p = 0; p < np && ok; ++p) {  // G of every panel
+    int j0, kb;
+    panel(n, p, j0, kb);
+    const int nr = n - (j0 + 1);
+    hipLaunchKernelGGL(k_vpanel, dim3(cdiv(nr * kb, 256)), dim3(256), 0, st, A, (long long)lda, n, j0, kb, V);
+    ok = gemm_tn_split(bh, st, kb, kb, nr, V, V, nr, PG, Gs + (size_t)p * kWY * kWY);
+  }
+  if (ok && np > 0) hipLaunchKernelGGL(k_larft, dim3(np), dim3(kLP * kWY), 0, st, Gs, tau, n, Ts);
+  for (int p = 0; p < np && ok; ++p) {  // the panels applied to Z, the last one first
+    int j0, kb;
+    panel(n, p, j0, kb);
     const int nr = n - (j0 + 1);
     double* Zr = Z + (j0 + 1);
+    const double* T = Ts + (size_t)p * kWY * kWY;
     hipLaunchKernelGGL(k_vpanel, dim3(cdiv(nr * kb, 256)), dim3(256), 0, st, A, (long long)lda, n, j0, kb, V);
-    ok = ok && gemm_tn_split(bh, st, kb, kb, nr, V, V, nr, PG, G);
-    hipLaunchKernelGGL(k_larft, dim3(1), dim3(kLP * kWY), 0, st, G, tau, j0, kb, T);
     ok = ok && gemm_tn_split(bh, st, kb, ncols, nr, V, Zr, ldz, PW, W);
     ok = ok && rocblas_dgemm(bh, nt, nt, kb, ncols, kb, &one, T, kb, W, kb, &zero, W2, kb) == rocblas_status_success;
     ok = ok &&
