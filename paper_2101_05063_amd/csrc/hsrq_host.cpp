@@ -504,20 +504,27 @@ int enqueue(hsrq_handle_t h, const Plan& P, int count, void* work, const void* h
   h->prof = prof;  // ProfScope reads the flag
   const ProbDesc* dd = at<ProbDesc>(work, P.o_desc);
   const Task* dt = at<Task>(work, P.o_tasks);
+  const int T = (int)P.coff.size();
+  hipStream_t a = h->aux;
+  hipEvent_t ev_fork = h->sync_ev[0], ev_crit = h->sync_ev[1], ev_far = h->sync_ev[2];
+  { ProfScope ps(h, HSRQ_K_PREP, s); launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s); }
+  // the input scan on the second stream beside init (they share no data;
+  // the scan needs the zeroed flags and norms, the first critical step the
+  // scan's tile norms)
+  hipEventRecord(ev_fork, s);
+  hipStreamWaitEvent(a, ev_fork, 0);
   {
-    ProfScope ps(h, HSRQ_K_PREP, s);
-    launch_fill(at<double>(work, P.o_zero_all), (long long)P.zero_count, 0.0, s);
-    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, P.nmax, s);
+    ProfScope ps(h, HSRQ_K_PREP, a);
+    launch_prep(dd, at<int4>(work, P.o_bprep), (int)P.blk_prep.size(), count, P.nmax, a);
   }
   { ProfScope ps(h, HSRQ_K_INIT, s); launch_init(dd, at<int4>(work, P.o_binit), (int)P.blk_init.size(), s); }
+  hipEventRecord(ev_far, a);
+  hipStreamWaitEvent(s, ev_far, 0);
   // steps: critical tasks on s, far tasks on the second stream; step t of
   // either kind waits for both kinds of step t-1.  (Letting the next
   // critical step start once only the far tile row next to the diagonal is
   // done was measured slower: the rest of the far tiles then hold the compute
   // units that the critical blocks, with their 83 KB of shared memory, need.)
-  const int T = (int)P.coff.size();
-  hipStream_t a = h->aux;
-  hipEvent_t ev_fork = h->sync_ev[0], ev_crit = h->sync_ev[1], ev_far = h->sync_ev[2];
   hipEventRecord(ev_fork, s);
   hipStreamWaitEvent(a, ev_fork, 0);
   for (int t = 0; t < T; ++t) {
