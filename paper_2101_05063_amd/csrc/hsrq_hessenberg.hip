@@ -35,6 +35,7 @@ namespace hsrq {
 namespace {
 
 constexpr int kT = 64;     // sweep tiles: 64 rows x 64 columns, 256 threads
+constexpr double kNTBytes = 256.0 * 1024 * 1024;  // sweeps past this size use non-temporal hints
 constexpr int kCH = 1024;  // threads of k_colhouse
 
 __device__ __forceinline__ double wsum(double x) {
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(kCH) k_colhouse_r(double* A, long long lda, in
 // u1(r) A(r, c).  k = -1 with UPD false: the partial sums of step 0.  The
 // per-column values are wave-uniform; the 16 loads of a lane are issued
 // before any of them is used.
-template <bool UPD, bool ACC>
+template <bool UPD, bool ACC, bool NT>
 __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long lda, int n, int k,
                                                const double* __restrict__ tau, const double* __restrict__ u0,
                                                const double* __restrict__ u1, const double* __restrict__ y,
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long
 #pragma unroll
   for (int j = 0; j < kCW; ++j) {
     const int c = cb + j < n ? cb + j : n - 1;  // clamped: columns past n are never stored
-    a[j] = A[(long long)c * lda + rr];
+    a[j] = NT ? __builtin_nontemporal_load(&A[(long long)c * lda + rr]) : A[(long long)c * lda + rr];
     if (UPD) {
       uc[j] = u0[c - (k + 1)];
       wc[j] = fma(-ts, uc[j], z[c - (k + 1)]);
@@ -341,7 +342,12 @@ __global__ void __launch_bounds__(256) k_sweep(double* __restrict__ A, long long
     const bool cok = c < n;  // uniform over the wave
     if (UPD) {
       a[j] = rank2(a[j], tyr, uc[j], tur, wc[j]);
-      if (rok && cok) A[(long long)c * lda + r] = a[j];
+      if (rok && cok) {
+        if (NT)
+          __builtin_nontemporal_store(a[j], &A[(long long)c * lda + r]);
+        else
+          A[(long long)c * lda + r] = a[j];
+      }
     }
     const double uv = (rok && cok) ? a[j] : 0.0;
     if (ACC) {
@@ -539,7 +545,7 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
   if (n >= 3) {
     // the reflector of column 0 and the partial sums of step 0
     colhouse(st, A, ld, n, -1, tau, u[1], u[0], y, z, sc);
-    hipLaunchKernelGGL((k_sweep<false, true>), dim3(nrt, cdiv(n - 1, kT)), dim3(256), 0, st, A, ld, n, -1, tau,
+    hipLaunchKernelGGL((k_sweep<false, true, false>), dim3(nrt, cdiv(n - 1, kT)), dim3(256), 0, st, A, ld, n, -1, tau,
                        u[1], u[0], y, z, sc, py, pz);
     for (int q = 0; q <= n - 3; ++q) {
       const int m = n - q - 1;  // rows and columns q+1 .. n-1
@@ -549,12 +555,21 @@ int gehrd(hipStream_t st, int n, double* A, int lda, double* tau, void* work) {
       const int nc = n - q - 2;  // columns q+2 .. n-1
       if (nc > 0) {
         const dim3 g(nrt, cdiv(nc, kT));
-        if (q + 1 <= n - 3)
-          hipLaunchKernelGGL((k_sweep<true, true>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
+        // trailing columns larger than kNTBytes are read and written with
+        // non-temporal hints (they are streamed once per step and do not
+        // stay in the caches until the next step anyway)
+        const bool nt = (double)sizeof(double) * n * nc > kNTBytes;
+        if (q + 1 <= n - 3) {
+          if (nt)
+            hipLaunchKernelGGL((k_sweep<true, true, true>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
+                               u[(q + 1) & 1], y, z, sc, py, pz);
+          else
+            hipLaunchKernelGGL((k_sweep<true, true, false>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
+                               u[(q + 1) & 1], y, z, sc, py, pz);
+        } else {
+          hipLaunchKernelGGL((k_sweep<true, false, false>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
                              u[(q + 1) & 1], y, z, sc, py, pz);
-        else
-          hipLaunchKernelGGL((k_sweep<true, false>), g, dim3(256), 0, st, A, ld, n, q, tau, u[q & 1],
-                             u[(q + 1) & 1], y, z, sc, py, pz);
+        }
       }
     }
   }
