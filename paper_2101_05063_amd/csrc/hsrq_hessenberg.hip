@@ -18,11 +18,16 @@
 // forms the partial sums of y and z for step k+1 (whose reflector is known
 // once column k+1 alone has been updated).  Per column:
 //   k_reduce      y, z of step k from the partial sums (fixed order)
-//   k_colhouse    s; column k+1 updated; the reflector of column k+1
+//   k_colhouse_r  s; column k+1 updated; the reflector of column k+1 (the
+//                 column in registers; k_colhouse above 8192 rows)
 //   k_sweep       columns k+2..n-1 updated; partial sums for step k+1
+//                 (non-temporal accesses while the trailing part is large)
 // Every reduction has a fixed order, so the results are the same on every
 // run.  The back-transform is blocked (compact WY): panels of 128
-// reflectors, each applied with matrix products on rocBLAS.
+// reflectors; k_vpanel makes a panel explicit, k_larft builds the
+// triangular factor T of every panel in one launch, and the products with
+// the vectors run on rocBLAS DGEMM (k_sumsplit adds the row-chunk partials
+// of the short, wide products).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
